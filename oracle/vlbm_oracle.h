@@ -1,0 +1,101 @@
+/*
+ * Plain FP64 CPU oracle of the blended D2Q5 vectorial lattice Boltzmann
+ * scheme (Wissocq, Liu, Abgrall, "A positive- and bound-preserving vectorial
+ * lattice Boltzmann method in two dimensions").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header or constant with the HIP library and never touches a GPU.
+ *
+ * State layout used by every entry point: S[20][ny][nx] (float64), plane
+ * s*4 + c holds slot s in {u, u_1, u_2, u_3, u_4} (the moment slot u replaces
+ * u_5, eq. (27)) and component c in {rho, m1, m2, E}.
+ *
+ * Face arrays: theta_x[ny][nx+1], entry (j, i) is the blending factor of the
+ * x-face between cells (i-1, j) and (i, j); theta_y[ny+1][nx], entry (j, i) is
+ * the factor of the y-face between cells (i, j-1) and (i, j).
+ */
+#ifndef VLBM_ORACLE_H
+#define VLBM_ORACLE_H
+
+#include <stdint.h>
+
+#define ORC_RHO_PP 1u
+#define ORC_RHO_LMP 2u
+#define ORC_RHO_RLMP 4u
+#define ORC_PRESSURE 8u
+
+#define ORC_A_DYNAMIC 0
+#define ORC_A_FIXED 1
+
+#define ORC_BC_PERIODIC 0
+#define ORC_BC_OUTFLOW 1
+
+typedef struct {
+  int32_t nx, ny;
+  double dx;
+  double gamma, alpha;
+  int32_t order;     /* 1: first-order scheme (theta = 0); 2: blended scheme */
+  uint32_t limiters; /* ORC_RHO_* | ORC_PRESSURE; 0 with order 2 = unlimited */
+  int32_t a_mode;    /* ORC_A_DYNAMIC: a = 2 beta lambda / (1 - alpha) */
+  double a_beta, a_fixed;
+  int32_t bc_x, bc_y;
+  int32_t sponge;    /* theta = 0 on faces touching this many cells at an outflow wall */
+  double eps, rlmp_lo, rlmp_hi;
+} orc_params;
+
+typedef struct {
+  double lambda;     /* lambda^n of the input state */
+  double a, dt, kappa;
+  double lambda_new; /* lambda^{n+1} of the output state */
+  int64_t n_guard;   /* faces whose intermediate state left the admissible set */
+  int64_t n_limited; /* faces with theta < 1 (left and bottom faces of every cell) */
+  int64_t n_bad;     /* output cells with rho <= 0, p <= 0 or non-finite wavespeed */
+  int32_t bouchut;   /* 1 if a < 2 lambda / (1 - alpha) */
+} orc_info;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Flux and Maxwellians of one state; M is [4][4] (k = 1..4, component). */
+void orc_flux(const double u[4], double gamma, double f[4], double g[4]);
+void orc_maxwellians(const double u[4], double gamma, double alpha, double a,
+                     double M[20]);
+/* Face limiters of Section 3.3 / 3.4 for a single face. */
+double orc_theta_rho_pp(double rho_star, double D, double kappa, double eps);
+double orc_theta_rho_lmp(double rho_star, double D, double kappa, double muL,
+                         double nuL, double muR, double nuR);
+double orc_theta_p(const double ustar[4], const double dF[4], double kappa,
+                   double eps);
+
+/* Maximum wavespeed over cells of the moment slot; *nbad counts cells that
+ * are not admissible (they are left out of the maximum). */
+double orc_lambda(const orc_params* P, const double* S, int64_t* nbad);
+/* Kinetic speed a^n for a given lambda^n. */
+double orc_kinetic_speed(const orc_params* P, double lambda);
+
+int orc_init(const orc_params* P, const double* u0, double* S, orc_info* info);
+int orc_step(const orc_params* P, const double* S, double* Snew,
+             double* theta_x, double* theta_y, orc_info* info);
+int orc_run(const orc_params* P, double* S, double* work, int32_t nsteps,
+            double* t, orc_info* last, int64_t totals[3]);
+
+/* The step map with theta and a given (frozen). */
+int orc_step_frozen(const orc_params* P, const double* S, const double* theta_x,
+                    const double* theta_y, double a, double* Snew);
+/* Complex-step evaluation of the same frozen maps: inputs S + i*Sim, outputs
+ * real and imaginary parts. */
+int orc_step_frozen_cs(const orc_params* P, const double* S, const double* Sim,
+                       const double* theta_x, const double* theta_y, double a,
+                       double* Snew, double* Snew_im);
+int orc_init_frozen_cs(const orc_params* P, const double* u0,
+                       const double* u0_im, double a, double* S, double* Sim);
+
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif
