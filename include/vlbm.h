@@ -1,0 +1,198 @@
+/*
+ * vlbm.h - C ABI of the MI355X (gfx950) library for the positive- and
+ * bound-preserving blended D2Q5 vectorial lattice Boltzmann scheme for the 2D
+ * compressible Euler equations (Wissocq, Liu, Abgrall).
+ *
+ * Every time step is one fused collide-limit-stream kernel launch:
+ *   - Maxwellians M_k (Example 1) and non-equilibrium parts d_k = M_k - u_k;
+ *   - face intermediate states u* (eq. (12)) and anti-diffusive fluxes
+ *     Delta F, Delta G (eq. (22));
+ *   - density limiter theta^rho (PP, LMP or RLMP, Section 3.3) and the
+ *     pressure-positivity limiter theta^p (Section 3.4), theta = min(1, ...);
+ *   - blended update of u_1..u_4 (eq. (25)) and of the moment slot that
+ *     replaces u_5 (eq. (27));
+ *   - the maximum wavespeed lambda^{n+1} of the new state, which sets the next
+ *     kinetic speed a^{n+1} = 2 beta lambda / (1 - alpha) (Section 4 preamble,
+ *     Proposition 3) without a host synchronisation.
+ *
+ * Memory: the caller owns all device memory.  It passes one workspace buffer
+ * of lbm_workspace_bytes() (or lbm_batch_workspace_bytes()) bytes, 256-byte
+ * aligned, that must stay allocated until lbm_destroy(); the library carves it
+ * into two state buffers, per-instance scalar slots and counters.  The library
+ * allocates only its small host context.  It never allocates device memory.
+ *
+ * State layout (what lbm_get_state / lbm_set_state / lbm_step_adjoint use):
+ * 20 planes, plane q = s*4 + c for slot s in {u, u_1, u_2, u_3, u_4} and
+ * component c in {rho, m1, m2, E}; each plane holds the instances one after
+ * the other, instance i as [ny_i][nx_i] row-major.  Element type: float64
+ * (LBM_FP64) or float32 (LBM_FP32_STATE).
+ *
+ * Streams: every enqueueing call is asynchronous on the stream given to the
+ * init call (a hipStream_t passed as void*; NULL = default stream).  A context
+ * is bound to that stream and is not thread-safe.  Calls never abort or throw:
+ * they return an lbm_status; lbm_last_error() describes the last failure.
+ * Events found on the device (non-admissible cells, a face state leaving the
+ * admissible set, a kinetic speed below the Bouchut bound) are counted and
+ * reported by the next synchronising call (lbm_moments, lbm_diagnostics).
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = 1,      /* invalid argument (parameters, pointers, sizes) */
+  LBM_ENOTSUP = 2,     /* valid but not supported by this entry point */
+  LBM_EDEVICE = 3,     /* a HIP runtime call failed */
+  LBM_EPOSITIVITY = 4, /* a cell with rho <= 0 or p <= 0 was produced */
+  LBM_ENONFINITE = 5,  /* reserved: non-finite values are reported as EPOSITIVITY */
+  LBM_EBOUCHUT = 6,    /* a < 2 lambda / (1 - alpha) in a fixed-a run (eq. (5)) */
+  LBM_EGUARD = 7       /* a face intermediate state u* left the admissible set */
+} lbm_status;
+
+/* Density limiters (Section 3.3) and the pressure limiter (Section 3.4). */
+#define LBM_RHO_PP 1u
+#define LBM_RHO_LMP 2u
+#define LBM_RHO_RLMP 4u
+#define LBM_PRESSURE 8u
+
+#define LBM_A_DYNAMIC 0 /* a^n = 2 beta lambda^n / (1 - alpha) */
+#define LBM_A_FIXED 1   /* a^n = a_fixed (Section 4.1) */
+
+#define LBM_BC_PERIODIC 0
+#define LBM_BC_OUTFLOW 1 /* zero gradient of every distribution (Section 4.2) */
+
+#define LBM_FP64 0
+#define LBM_FP32_STATE 1 /* float32 state and collide/stream arithmetic; the
+                            theta solve and the wavespeed reduction in float64 */
+
+typedef struct {
+  int32_t nx, ny;     /* cells; >= 1 */
+  double dx;          /* square cells; cell centres at (i + 1/2) dx */
+  double gamma;       /* ideal-gas ratio, > 1 */
+  double alpha;       /* rest weight of the D2Q5 model, in [1/2, 1) (Prop. 3) */
+  int32_t order;      /* 1: first-order scheme (theta = 0); 2: blended scheme */
+  uint32_t limiters;  /* LBM_RHO_* | LBM_PRESSURE; 0 with order 2 = unlimited */
+  int32_t a_mode;     /* LBM_A_DYNAMIC or LBM_A_FIXED */
+  double a_beta;      /* beta >= 1 for LBM_A_DYNAMIC */
+  double a_fixed;     /* kinetic speed for LBM_A_FIXED, > 0 */
+  int32_t bc_x, bc_y; /* LBM_BC_* per axis */
+  int32_t sponge;     /* theta = 0 on faces touching the first `sponge` cells
+                         of an outflow wall (Section 4.2); 0 = none */
+  int32_t precision;  /* LBM_FP64 or LBM_FP32_STATE */
+  double eps;         /* epsilon of the PP and pressure limiters (1e-16) */
+  double rlmp_lo, rlmp_hi; /* relaxed bound factors (0.999, 1.001) */
+  double theta_margin;/* LBM_FP32_STATE only: kappa is scaled by (1 - margin)
+                         in the limiters; must be 0 for LBM_FP64 */
+  int32_t unsafe;     /* 1 allows alpha < 1/2 or beta < 1 (no positivity
+                         guarantee); 0 rejects them */
+} lbm_params;
+
+typedef struct {
+  double lambda;       /* lambda^n of the current state (instance 0 / inst) */
+  double a;            /* a^n that the next step will use */
+  double t;            /* accumulated time t^n */
+  int64_t step;        /* steps taken since init */
+  int64_t n_guard;     /* faces with u* outside the admissible set */
+  int64_t n_limited;   /* faces with theta < 1 (left and bottom face of every cell) */
+  int64_t n_bad;       /* cells with rho <= 0, p <= 0 or a non-finite wavespeed */
+  int32_t bouchut;     /* a fixed a fell below 2 lambda / (1 - alpha) */
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of workspace for one instance / a batch of n instances (sizes nx[i],
+ * ny[i]; all other parameters shared).  0 on invalid arguments. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n,
+                                 const int32_t* nx, const int32_t* ny);
+
+/* Initialisation (Section 4 preamble): the moment slot takes u0 and
+ * u_k = M_k(u0; a^0), k = 1..4, with lambda^0 and a^0 from u0.
+ * u0_dev: float64 [4][ny][nx] (rho, m1, m2, E), device memory, read only.
+ * Synchronises once to check that every cell of u0 is admissible
+ * (LBM_EPOSITIVITY otherwise; no context is returned).  On success *out owns a
+ * host context bound to `stream` (free with lbm_destroy). */
+lbm_status lbm_init(const lbm_params* p, const double* u0_dev, void* workspace_dev,
+                    void* stream, lbm_ctx** out);
+
+/* Batch of n independent instances sharing every parameter except nx, ny and
+ * dx (dx[i] = 1/nx[i] when dx_host is NULL).  u0_packed_dev concatenates the
+ * instances' float64 [4][ny_i][nx_i] blocks. */
+lbm_status lbm_init_batch(const lbm_params* p, int32_t n, const int32_t* nx,
+                          const int32_t* ny, const double* dx_host,
+                          const double* u0_packed_dev, void* workspace_dev,
+                          void* stream, lbm_ctx** out);
+
+/* nsteps time steps (eqs. (25), (27) with the limiters of Section 3), one
+ * kernel launch each, asynchronous, no host synchronisation. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Same steps, replayed from a hipGraph that holds nsteps launches (captured
+ * on first use for each (nsteps, phase) and cached in the context). */
+lbm_status lbm_step_graph(lbm_ctx* ctx, int32_t nsteps);
+
+/* One step that also writes the face factors: theta_x_dev float64
+ * [ny][nx + 1] (x-face between cells (i-1, j) and (i, j)), theta_y_dev
+ * float64 [ny + 1][nx] (y-face between (i, j-1) and (i, j)).  Single
+ * instance only. */
+lbm_status lbm_step_theta(lbm_ctx* ctx, double* theta_x_dev, double* theta_y_dev);
+
+/* Moments (rho, m1, m2, E) of instance `inst` as float64 [4][ny][nx] into
+ * u_out_dev.  Synchronises the stream; returns the first device event counted
+ * since the last synchronising call (LBM_EPOSITIVITY, LBM_EGUARD,
+ * LBM_EBOUCHUT) or LBM_OK, and clears the counters. */
+lbm_status lbm_moments(lbm_ctx* ctx, int32_t inst, double* u_out_dev);
+
+/* Diagnostics of instance `inst`; synchronises; does not clear counters. */
+lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t inst, lbm_diag* out);
+
+/* Copy the whole current state (layout above, lbm_state_bytes bytes) to /
+ * from caller device memory; set_state also sets lambda^n from the new state
+ * (so the next step's a^n follows it) and keeps t and the step count. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_get_state(lbm_ctx* ctx, void* dst_dev);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
+
+/* Adjoint of one step with the blending factors theta^n and the kinetic
+ * speed a^n held fixed at the values the forward step computes from U_n
+ * (they are recomputed from U_n with the forward code, bit for bit):
+ *   Ubar_n = (d S^{n+1} / d S^n)^T Ubar_np1.
+ * All three are float64 states in the layout above (single instance,
+ * LBM_FP64, periodic boundaries; LBM_ENOTSUP otherwise).  Uses the context's
+ * workspace as scratch; does not change the context's own state. */
+lbm_status lbm_step_adjoint(lbm_ctx* ctx, const double* U_n_dev,
+                            const double* Ubar_np1_dev, double* Ubar_n_dev);
+
+/* Adjoint of the initialisation map u0 -> (u0, M_1..M_4(u0; a^0)) with a^0
+ * held fixed: u0bar = Ubar0[u] + sum_k J_{M_k}(u0)^T Ubar0[u_k].
+ * u0 and u0bar: float64 [4][ny][nx]; Ubar0: float64 state. */
+lbm_status lbm_init_adjoint(lbm_ctx* ctx, const double* u0_dev,
+                            const double* Ubar0_dev, double* u0bar_dev);
+
+/* Times the step kernel for the candidate strip heights and waves per
+ * workgroup on the context's own problem (advancing its state by the steps
+ * it runs), keeps the fastest and records it in a JSON cache file keyed by
+ * problem shape (NULL path = no file).  Synchronises. */
+lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
+
+/* Launch shape of the step kernel: rows per strip and waves per workgroup
+ * (0 keeps the current value). */
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t strip_rows, int32_t waves_per_group);
+lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* waves_per_group);
+
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(const lbm_ctx* ctx);
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

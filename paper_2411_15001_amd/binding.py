@@ -1,0 +1,288 @@
+"""ctypes binding of libvlbm.so (include/vlbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  Device memory comes from torch tensors on a ROCm device and
+the stream is torch's current stream.  If the library has not been built the
+import of a binding function raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvlbm.so")
+
+LBM_OK = 0
+LBM_EINVAL = 1
+LBM_ENOTSUP = 2
+LBM_EDEVICE = 3
+LBM_EPOSITIVITY = 4
+LBM_ENONFINITE = 5
+LBM_EBOUCHUT = 6
+LBM_EGUARD = 7
+
+LBM_RHO_PP = 1
+LBM_RHO_LMP = 2
+LBM_RHO_RLMP = 4
+LBM_PRESSURE = 8
+LBM_A_DYNAMIC = 0
+LBM_A_FIXED = 1
+LBM_BC_PERIODIC = 0
+LBM_BC_OUTFLOW = 1
+LBM_FP64 = 0
+LBM_FP32_STATE = 1
+
+EXPORTS = [
+    "lbm_workspace_bytes", "lbm_batch_workspace_bytes", "lbm_init", "lbm_init_batch",
+    "lbm_step", "lbm_step_graph", "lbm_step_theta", "lbm_moments", "lbm_diagnostics",
+    "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_adjoint",
+    "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
+    "lbm_status_string", "lbm_last_error", "lbm_destroy",
+]
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("order", ctypes.c_int32), ("limiters", ctypes.c_uint32),
+        ("a_mode", ctypes.c_int32),
+        ("a_beta", ctypes.c_double), ("a_fixed", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("sponge", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("rlmp_lo", ctypes.c_double), ("rlmp_hi", ctypes.c_double),
+        ("theta_margin", ctypes.c_double),
+        ("unsafe", ctypes.c_int32),
+    ]
+
+
+class lbm_diag(ctypes.Structure):
+    _fields_ = [
+        ("lam", ctypes.c_double), ("a", ctypes.c_double), ("t", ctypes.c_double),
+        ("step", ctypes.c_int64), ("n_guard", ctypes.c_int64),
+        ("n_limited", ctypes.c_int64), ("n_bad", ctypes.c_int64),
+        ("bouchut", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvlbm.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2411_15001_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        pp = ctypes.POINTER(lbm_params)
+        i32 = ctypes.c_int32
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.lbm_workspace_bytes.argtypes = [pp]
+        L.lbm_workspace_bytes.restype = ctypes.c_size_t
+        L.lbm_batch_workspace_bytes.argtypes = [pp, i32, i32p, i32p]
+        L.lbm_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.lbm_init.argtypes = [pp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.lbm_init_batch.argtypes = [pp, i32, i32p, i32p, ctypes.POINTER(ctypes.c_double), vp, vp,
+                                     vp, ctypes.POINTER(vp)]
+        L.lbm_step.argtypes = [vp, i32]
+        L.lbm_step_graph.argtypes = [vp, i32]
+        L.lbm_step_theta.argtypes = [vp, vp, vp]
+        L.lbm_moments.argtypes = [vp, i32, vp]
+        L.lbm_diagnostics.argtypes = [vp, i32, ctypes.POINTER(lbm_diag)]
+        L.lbm_state_bytes.argtypes = [vp]
+        L.lbm_state_bytes.restype = ctypes.c_size_t
+        L.lbm_get_state.argtypes = [vp, vp]
+        L.lbm_set_state.argtypes = [vp, vp]
+        L.lbm_step_adjoint.argtypes = [vp, vp, vp, vp]
+        L.lbm_init_adjoint.argtypes = [vp, vp, vp, vp]
+        L.lbm_autotune.argtypes = [vp, ctypes.c_char_p]
+        L.lbm_set_launch.argtypes = [vp, i32, i32]
+        L.lbm_get_launch.argtypes = [vp, i32p, i32p]
+        L.lbm_status_string.argtypes = [ctypes.c_int]
+        L.lbm_status_string.restype = ctypes.c_char_p
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is ctypes.c_int:  # the default: status codes
+                f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (lib().lbm_status_string(status).decode(), status, message))
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != LBM_OK:
+        msg = lib().lbm_last_error(ctx).decode()
+        raise LbmError(status, msg)
+    return status
+
+
+def make_params(nx, ny, dx=None, gamma=1.4, alpha=0.5, order=2,
+                limiters=LBM_RHO_PP | LBM_PRESSURE, a_mode=LBM_A_DYNAMIC, a_beta=1.0,
+                a_fixed=0.0, bc_x=LBM_BC_PERIODIC, bc_y=LBM_BC_PERIODIC, sponge=0,
+                precision=LBM_FP64, eps=1e-16, rlmp_lo=0.999, rlmp_hi=1.001,
+                theta_margin=0.0, unsafe=0):
+    return lbm_params(nx, ny, 1.0 / nx if dx is None else dx, gamma, alpha, order, limiters,
+                      a_mode, a_beta, a_fixed, bc_x, bc_y, sponge, precision, eps, rlmp_lo,
+                      rlmp_hi, theta_margin, unsafe)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_cuda(t, dtype=None):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("expected dtype %s, got %s" % (dtype, t.dtype))
+
+
+# --------------------------------------------------------------------------
+# Functions with the names of the C ABI
+# --------------------------------------------------------------------------
+
+def lbm_workspace_bytes(params):
+    return lib().lbm_workspace_bytes(ctypes.byref(params))
+
+
+def lbm_batch_workspace_bytes(params, nx, ny):
+    n = len(nx)
+    ax = (ctypes.c_int32 * n)(*nx)
+    ay = (ctypes.c_int32 * n)(*ny)
+    return lib().lbm_batch_workspace_bytes(ctypes.byref(params), n, ax, ay)
+
+
+def lbm_init(params, u0, workspace):
+    import torch
+
+    _require_cuda(u0, torch.float64)
+    _require_cuda(workspace)
+    ctx = ctypes.c_void_p()
+    _check(lib().lbm_init(ctypes.byref(params), _ptr(u0), _ptr(workspace), _stream(),
+                          ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_init_batch(params, nx, ny, u0_packed, workspace, dx=None):
+    import torch
+
+    _require_cuda(u0_packed, torch.float64)
+    _require_cuda(workspace)
+    n = len(nx)
+    ax = (ctypes.c_int32 * n)(*nx)
+    ay = (ctypes.c_int32 * n)(*ny)
+    adx = (ctypes.c_double * n)(*dx) if dx is not None else None
+    ctx = ctypes.c_void_p()
+    _check(lib().lbm_init_batch(ctypes.byref(params), n, ax, ay, adx, _ptr(u0_packed),
+                                _ptr(workspace), _stream(), ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_step(ctx, nsteps):
+    return _check(lib().lbm_step(ctx, int(nsteps)), ctx)
+
+
+def lbm_step_graph(ctx, nsteps):
+    return _check(lib().lbm_step_graph(ctx, int(nsteps)), ctx)
+
+
+def lbm_step_theta(ctx, theta_x, theta_y):
+    import torch
+
+    _require_cuda(theta_x, torch.float64)
+    _require_cuda(theta_y, torch.float64)
+    return _check(lib().lbm_step_theta(ctx, _ptr(theta_x), _ptr(theta_y)), ctx)
+
+
+def lbm_moments(ctx, inst, out, check=True):
+    import torch
+
+    _require_cuda(out, torch.float64)
+    st = lib().lbm_moments(ctx, int(inst), _ptr(out))
+    if check:
+        _check(st, ctx)
+    return st
+
+
+def lbm_diagnostics(ctx, inst=0):
+    d = lbm_diag()
+    _check(lib().lbm_diagnostics(ctx, int(inst), ctypes.byref(d)), ctx)
+    return d
+
+
+def lbm_state_bytes(ctx):
+    return lib().lbm_state_bytes(ctx)
+
+
+def lbm_get_state(ctx, dst):
+    _require_cuda(dst)
+    return _check(lib().lbm_get_state(ctx, _ptr(dst)), ctx)
+
+
+def lbm_set_state(ctx, src):
+    _require_cuda(src)
+    return _check(lib().lbm_set_state(ctx, _ptr(src)), ctx)
+
+
+def lbm_step_adjoint(ctx, U_n, Ubar_np1, Ubar_n):
+    import torch
+
+    for t in (U_n, Ubar_np1, Ubar_n):
+        _require_cuda(t, torch.float64)
+    return _check(lib().lbm_step_adjoint(ctx, _ptr(U_n), _ptr(Ubar_np1), _ptr(Ubar_n)), ctx)
+
+
+def lbm_init_adjoint(ctx, u0, Ubar0, u0bar):
+    import torch
+
+    for t in (u0, Ubar0, u0bar):
+        _require_cuda(t, torch.float64)
+    return _check(lib().lbm_init_adjoint(ctx, _ptr(u0), _ptr(Ubar0), _ptr(u0bar)), ctx)
+
+
+def lbm_autotune(ctx, cache_path=None):
+    p = cache_path.encode() if cache_path else None
+    return _check(lib().lbm_autotune(ctx, p), ctx)
+
+
+def lbm_set_launch(ctx, strip_rows=0, waves_per_group=0):
+    return _check(lib().lbm_set_launch(ctx, int(strip_rows), int(waves_per_group)), ctx)
+
+
+def lbm_get_launch(ctx):
+    r = ctypes.c_int32()
+    w = ctypes.c_int32()
+    _check(lib().lbm_get_launch(ctx, ctypes.byref(r), ctypes.byref(w)), ctx)
+    return r.value, w.value
+
+
+def lbm_last_error(ctx=None):
+    return lib().lbm_last_error(ctx).decode()
+
+
+def lbm_destroy(ctx):
+    lib().lbm_destroy(ctx)

@@ -1,0 +1,50 @@
+"""Build the HIP library libvlbm.so in-tree for gfx950 with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB_PATH = os.path.join(HERE, "libvlbm.so")
+SOURCES = [os.path.join(CSRC, f) for f in ("step.hip", "adjoint.hip", "api.hip")]
+HEADERS = [os.path.join(CSRC, "vlbm_internal.h"), os.path.join(ROOT, "include", "vlbm.h")]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # no contraction into FMAs: the float64 path reproduces the oracle's
+    # rounding operation by operation
+    "-ffp-contract=off",
+    # no packed fp32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def build_library(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = [hipcc] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC] + SOURCES + [
+        "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    if verbose:
+        print(r.stderr)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def stale() -> bool:
+    if not os.path.exists(LIB_PATH):
+        return True
+    newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
+    return os.path.getmtime(LIB_PATH) < newest
+
+
+if __name__ == "__main__":
+    print(build_library(verbose=True))

@@ -1,0 +1,169 @@
+// Adjoint of one blended step and of the initialisation, FP64, periodic.
+//
+// With theta and a held fixed, the step (eqs. (25), (27)) is, per cell c with
+// face factors tW, tE, tS, tN (faces i-1/2, i+1/2, j-1/2, j+1/2):
+//   u_1'(c) = (1 + tW) M_1(u_W) - tW u_1(W),   u_2'(c) = (1 + tE) M_2(u_E) - tE u_2(E),
+//   u_3'(c) = (1 + tS) M_3(u_S) - tS u_3(S),   u_4'(c) = (1 + tN) M_4(u_N) - tN u_4(N),
+//   u'(c)   = alpha u + sum_k u_k'(c) - tW d_2(c) - tE d_1(c) - tS d_4(c) - tN d_3(c),
+// with d_k = M_k(u) - u_k and the Maxwellian Jacobians of Example 1,
+// J_{M_1,2} = w I +- A(u)/(2a), J_{M_3,4} = w I +- B(u)/(2a), A = f'(u),
+// B = g'(u).  Transposing this radius-1 stencil gives the gather below for
+// every cell x (g_k(c) = ubar_k'(c) + ubar'(c) is the adjoint reaching
+// u_k'(c), which enters both slot k and the moment sum):
+//   ubar(x)   = alpha ubar'(x) + J_{M_1}^T [(1 + tE) g_1(E) - tE ubar'(x)]
+//             + J_{M_2}^T [(1 + tW) g_2(W) - tW ubar'(x)]
+//             + J_{M_3}^T [(1 + tN) g_3(N) - tN ubar'(x)]
+//             + J_{M_4}^T [(1 + tS) g_4(S) - tS ubar'(x)],
+//   ubar_1(x) = tE (ubar'(x) - g_1(E)),  ubar_2(x) = tW (ubar'(x) - g_2(W)),
+//   ubar_3(x) = tN (ubar'(x) - g_3(N)),  ubar_4(x) = tS (ubar'(x) - g_4(S)).
+// The face factors come from the forward kernel run on the same state, so
+// they equal the forward step's bit for bit.
+
+#include "vlbm_internal.h"
+
+namespace vlbm {
+namespace {
+
+struct Jac {
+  double v1, v2, q, H, gm1, gamma;
+};
+
+__device__ __forceinline__ Jac jac_of(const double u[4], double gamma) {
+  Jac J;
+  const double ir = 1.0 / u[0];
+  J.v1 = u[1] * ir;
+  J.v2 = u[2] * ir;
+  J.q = 0.5 * (J.v1 * J.v1 + J.v2 * J.v2);
+  J.gm1 = gamma - 1.0;
+  J.gamma = gamma;
+  const double p = J.gm1 * (u[3] - u[0] * J.q);
+  J.H = (u[3] + p) * ir;
+  return J;
+}
+
+// A(u)^T z with A = df/du of the Euler x-flux.
+__device__ __forceinline__ void At(const Jac& J, const double z[4], double o[4]) {
+  const double v1 = J.v1, v2 = J.v2, k = J.gm1;
+  o[0] = (-v1 * v1 + k * J.q) * z[1] - v1 * v2 * z[2] + (-J.H * v1 + k * J.q * v1) * z[3];
+  o[1] = z[0] + (2.0 - k) * v1 * z[1] + v2 * z[2] + (J.H - k * v1 * v1) * z[3];
+  o[2] = -k * v2 * z[1] + v1 * z[2] - k * v1 * v2 * z[3];
+  o[3] = k * z[1] + J.gamma * v1 * z[3];
+}
+
+// B(u)^T z with B = dg/du of the Euler y-flux.
+__device__ __forceinline__ void Bt(const Jac& J, const double z[4], double o[4]) {
+  const double v1 = J.v1, v2 = J.v2, k = J.gm1;
+  o[0] = -v1 * v2 * z[1] + (-v2 * v2 + k * J.q) * z[2] + (-J.H * v2 + k * J.q * v2) * z[3];
+  o[1] = v2 * z[1] - k * v1 * z[2] - k * v1 * v2 * z[3];
+  o[2] = z[0] + v1 * z[1] + (2.0 - k) * v2 * z[2] + (J.H - k * v2 * v2) * z[3];
+  o[3] = k * z[2] + J.gamma * v2 * z[3];
+}
+
+__device__ __forceinline__ double kinetic_speed(const Scheme& s, const Slots* sl, int slot) {
+  const double lam = __longlong_as_double((long long)sl->lam[slot]);
+  return (s.a_mode == 1) ? s.a_fixed : 2.0 * s.beta * lam / (1.0 - s.alpha);
+}
+
+__global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, int ny, long long P,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ B1,
+                                                           double* __restrict__ B0,
+                                                           const double* __restrict__ tx,
+                                                           const double* __restrict__ ty,
+                                                           const Slots* sl, int slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= nx || j >= ny) return;
+  const double a = kinetic_speed(sc, sl, slot);
+  const double w = 0.25 * (1.0 - sc.alpha);
+  const double r2a = 1.0 / (2.0 * a);
+  const int iw = i == 0 ? nx - 1 : i - 1, ie = i == nx - 1 ? 0 : i + 1;
+  const int js = j == 0 ? ny - 1 : j - 1, jn = j == ny - 1 ? 0 : j + 1;
+  const long long cX = (long long)j * nx + i;
+  const long long cW = (long long)j * nx + iw, cE = (long long)j * nx + ie;
+  const long long cS = (long long)js * nx + i, cN = (long long)jn * nx + i;
+  const double tW = tx[(long long)j * (nx + 1) + i], tE = tx[(long long)j * (nx + 1) + i + 1];
+  const double tS = ty[(long long)j * nx + i], tN = ty[(long long)(j + 1) * nx + i];
+  double u[4], ub[4], g1[4], g2[4], g3[4], g4[4];
+  for (int c = 0; c < 4; ++c) {
+    u[c] = U[c * P + cX];
+    ub[c] = B1[c * P + cX];
+    g1[c] = B1[(4 + c) * P + cE] + B1[c * P + cE];
+    g2[c] = B1[(8 + c) * P + cW] + B1[c * P + cW];
+    g3[c] = B1[(12 + c) * P + cN] + B1[c * P + cN];
+    g4[c] = B1[(16 + c) * P + cS] + B1[c * P + cS];
+  }
+  const Jac J = jac_of(u, sc.gamma);
+  double z1[4], z2[4], z3[4], z4[4];
+  for (int c = 0; c < 4; ++c) {
+    z1[c] = (1.0 + tE) * g1[c] - tE * ub[c];
+    z2[c] = (1.0 + tW) * g2[c] - tW * ub[c];
+    z3[c] = (1.0 + tN) * g3[c] - tN * ub[c];
+    z4[c] = (1.0 + tS) * g4[c] - tS * ub[c];
+  }
+  double dx[4], dy[4], ax[4], by[4];
+  for (int c = 0; c < 4; ++c) {
+    dx[c] = z1[c] - z2[c];
+    dy[c] = z3[c] - z4[c];
+  }
+  At(J, dx, ax);
+  Bt(J, dy, by);
+  for (int c = 0; c < 4; ++c) {
+    B0[c * P + cX] = sc.alpha * ub[c] + w * (z1[c] + z2[c] + z3[c] + z4[c]) + r2a * (ax[c] + by[c]);
+    B0[(4 + c) * P + cX] = tE * (ub[c] - g1[c]);
+    B0[(8 + c) * P + cX] = tW * (ub[c] - g2[c]);
+    B0[(12 + c) * P + cX] = tN * (ub[c] - g3[c]);
+    B0[(16 + c) * P + cX] = tS * (ub[c] - g4[c]);
+  }
+}
+
+// u0bar = Ubar0[u] + sum_k J_{M_k}(u0)^T Ubar0[u_k] with a^0 fixed.
+__global__ __launch_bounds__(256) void adjoint_init_kernel(Scheme sc, long long n,
+                                                           const double* __restrict__ u0,
+                                                           const double* __restrict__ B,
+                                                           double* __restrict__ out,
+                                                           const Slots* sl, int slot) {
+  const long long c0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c0 >= n) return;
+  const double a = kinetic_speed(sc, sl, slot);
+  const double w = 0.25 * (1.0 - sc.alpha);
+  const double r2a = 1.0 / (2.0 * a);
+  double u[4], b[5][4];
+  for (int c = 0; c < 4; ++c) {
+    u[c] = u0[c * n + c0];
+    for (int s = 0; s < 5; ++s) b[s][c] = B[(4 * s + c) * n + c0];
+  }
+  const Jac J = jac_of(u, sc.gamma);
+  double dx[4], dy[4], ax[4], by[4];
+  for (int c = 0; c < 4; ++c) {
+    dx[c] = b[1][c] - b[2][c];
+    dy[c] = b[3][c] - b[4][c];
+  }
+  At(J, dx, ax);
+  Bt(J, dy, by);
+  for (int c = 0; c < 4; ++c)
+    out[c * n + c0] = b[0][c] + w * (b[1][c] + b[2][c] + b[3][c] + b[4][c]) + r2a * (ax[c] + by[c]);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane, const double* U,
+                               const double* Ub1, double* Ub0, const double* tx, const double* ty,
+                               const Slots* slots, int slot, hipStream_t s) {
+  const dim3 block(256);
+  const dim3 grid((in.nx + 255) / 256, in.ny);
+  hipLaunchKernelGGL(adjoint_step_kernel, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1, Ub0,
+                     tx, ty, slots, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const Scheme& sc, const Inst& in, const double* u0,
+                               const double* Ub0, double* u0b, const Slots* slots, int slot,
+                               hipStream_t s) {
+  const long long n = (long long)in.nx * in.ny;
+  hipLaunchKernelGGL(adjoint_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sc, n,
+                     u0, Ub0, u0b, slots, slot);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm

@@ -1,0 +1,709 @@
+// Host side of the C ABI declared in include/vlbm.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "vlbm.h"
+#include "vlbm_internal.h"
+
+using vlbm::Inst;
+using vlbm::Scheme;
+using vlbm::Slots;
+
+namespace {
+
+constexpr int kMinStripRows = 16;  // bounds the work-item table in the workspace
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+thread_local std::string g_init_error;
+
+int halo_radius(const lbm_params* p) {
+  return (p->order == 2 && (p->limiters & (LBM_RHO_LMP | LBM_RHO_RLMP))) ? 2 : 1;
+}
+
+long long strips_x(int nx, int R) {
+  const int ow = 64 - 2 * R;
+  return (nx + ow - 1) / ow;
+}
+
+long long strips_y(int ny, int h) { return (ny + h - 1) / h; }
+
+const char* check_params(const lbm_params* p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+  if (!(p->dx > 0.0) || !isfinite(p->dx)) return "dx must be > 0";
+  if (!(p->gamma > 1.0)) return "gamma must be > 1";
+  if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return "alpha must lie in [0, 1)";
+  if (!p->unsafe && p->alpha < 0.5) return "alpha < 1/2 breaks the convex decomposition (set unsafe)";
+  if (p->order != 1 && p->order != 2) return "order must be 1 or 2";
+  if (p->limiters & ~15u) return "unknown limiter bits";
+  if (p->a_mode != LBM_A_DYNAMIC && p->a_mode != LBM_A_FIXED) return "unknown a_mode";
+  if (p->a_mode == LBM_A_DYNAMIC) {
+    if (!(p->a_beta > 0.0)) return "a_beta must be > 0";
+    if (!p->unsafe && p->a_beta < 1.0) return "a_beta < 1 violates the Bouchut condition (set unsafe)";
+  } else if (!(p->a_fixed > 0.0) || !isfinite(p->a_fixed)) {
+    return "a_fixed must be > 0";
+  }
+  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return "unknown boundary condition";
+  if (p->sponge < 0) return "sponge must be >= 0";
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32_STATE) return "unknown precision";
+  if (!(p->eps >= 0.0)) return "eps must be >= 0";
+  if (!(p->rlmp_lo > 0.0 && p->rlmp_lo <= 1.0 && p->rlmp_hi >= 1.0)) return "bad RLMP factors";
+  if (!(p->theta_margin >= 0.0 && p->theta_margin < 1.0)) return "theta_margin must lie in [0, 1)";
+  if (p->precision == LBM_FP64 && p->theta_margin != 0.0) return "theta_margin is for LBM_FP32_STATE only";
+  return nullptr;
+}
+
+Scheme make_scheme(const lbm_params* p) {
+  Scheme s;
+  s.gamma = p->gamma;
+  s.alpha = p->alpha;
+  s.beta = p->a_beta;
+  s.a_fixed = p->a_fixed;
+  s.eps = p->eps;
+  s.rlmp_lo = p->rlmp_lo;
+  s.rlmp_hi = p->rlmp_hi;
+  s.theta_margin = p->theta_margin;
+  s.a_mode = p->a_mode;
+  s.order = p->order;
+  s.limiters = (int)p->limiters;
+  s.bc_x = p->bc_x;
+  s.bc_y = p->bc_y;
+  s.sponge = p->sponge;
+  return s;
+}
+
+struct Layout {
+  size_t slots, insts, items, bufA, bufB, theta, total;
+};
+
+Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
+  const size_t elem = p->precision == LBM_FP64 ? 8 : 4;
+  const int R = halo_radius(p);
+  long long cells = 0, items = 0;
+  for (int i = 0; i < n; ++i) {
+    cells += (long long)nx[i] * ny[i];
+    items += strips_x(nx[i], R) * strips_y(ny[i], kMinStripRows);
+  }
+  Layout L;
+  size_t o = 0;
+  L.slots = o;
+  o = align_up(o + sizeof(Slots) * (size_t)n);
+  L.insts = o;
+  o = align_up(o + sizeof(Inst) * (size_t)n);
+  L.items = o;
+  o = align_up(o + sizeof(int) * (size_t)(n > 1 ? items : 0));
+  L.bufA = o;
+  o = align_up(o + (size_t)20 * cells * elem);
+  L.bufB = o;
+  o = align_up(o + (size_t)20 * cells * elem);
+  L.theta = o;
+  if (n == 1 && p->precision == LBM_FP64)  // theta faces for the adjoint
+    o = align_up(o + sizeof(double) * ((size_t)(nx[0] + 1) * ny[0] + (size_t)nx[0] * (ny[0] + 1)));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Scheme sc;
+  int n_inst = 0;
+  std::vector<Inst> insts;
+  std::vector<int> item_inst;
+  long long plane = 0;
+  long long n_items = 0;
+  char* ws = nullptr;
+  Layout lay;
+  Slots* slots = nullptr;
+  Inst* insts_dev = nullptr;
+  int* items_dev = nullptr;
+  hipStream_t stream = nullptr;
+  long long step = 0;
+  int strip_rows = 64;
+  int waves = 4;
+  int xcd = 1;
+  int persistent_groups = 0;  // > 0: persistent launch with this many groups
+  std::string err;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+
+  void* cur() const { return ws + ((step & 1) ? lay.bufB : lay.bufA); }
+  void* other() const { return ws + ((step & 1) ? lay.bufA : lay.bufB); }
+  size_t elem() const { return p.precision == LBM_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& m) {
+  if (c)
+    c->err = m;
+  else
+    g_init_error = m;
+  return s;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, LBM_EDEVICE, m);
+}
+
+// Rebuild the strip tables after a change of strip height.
+void build_items(lbm_ctx* c) {
+  const int R = halo_radius(&c->p);
+  c->n_items = 0;
+  c->item_inst.clear();
+  for (int i = 0; i < c->n_inst; ++i) {
+    Inst& in = c->insts[i];
+    in.xs = (int)strips_x(in.nx, R);
+    in.ys = (int)strips_y(in.ny, c->strip_rows);
+    in.item0 = c->n_items;
+    const long long k = (long long)in.xs * in.ys;
+    if (c->n_inst > 1)
+      for (long long q = 0; q < k; ++q) c->item_inst.push_back(i);
+    c->n_items += k;
+  }
+}
+
+lbm_status upload_tables(lbm_ctx* c) {
+  if (c->n_inst == 1) return LBM_OK;
+  hipError_t e = hipMemcpyAsync(c->insts_dev, c->insts.data(), sizeof(Inst) * c->n_inst,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->items_dev, c->item_inst.data(), sizeof(int) * c->item_inst.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "uploading strip tables");
+  return LBM_OK;
+}
+
+int compute_groups(const lbm_ctx* c) {
+  long long g = (c->n_items + c->waves - 1) / c->waves;
+  if (c->persistent_groups > 0 && g > c->persistent_groups) g = c->persistent_groups;
+  if (c->xcd) g = (g + 7) / 8 * 8;
+  return (int)g;
+}
+
+vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot) {
+  vlbm::StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.src = src;
+  a.dst = dst;
+  a.plane = c->plane;
+  a.slots = c->slots;
+  a.insts = c->insts_dev;
+  a.item_inst = c->n_inst > 1 ? c->items_dev : nullptr;
+  a.inst0 = c->insts[0];
+  a.n_items = c->n_items;
+  a.n_inst = c->n_inst;
+  a.slot = slot;
+  a.strip_h = c->strip_rows;
+  a.waves_per_group = c->waves;
+  a.xcd_remap = c->xcd;
+  a.groups = compute_groups(c);
+  a.sc = c->sc;
+  return a;
+}
+
+lbm_status launch_one(lbm_ctx* c) {
+  vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
+  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  c->step += 1;
+  return LBM_OK;
+}
+
+lbm_status read_slots(lbm_ctx* c, std::vector<Slots>& h) {
+  h.resize(c->n_inst);
+  hipError_t e = hipMemcpyAsync(h.data(), c->slots, sizeof(Slots) * c->n_inst,
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reading device slots");
+  return LBM_OK;
+}
+
+lbm_status write_slots(lbm_ctx* c, const std::vector<Slots>& h) {
+  hipError_t e = hipMemcpyAsync(c->slots, h.data(), sizeof(Slots) * c->n_inst,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "writing device slots");
+  return LBM_OK;
+}
+
+double host_kinetic_speed(const lbm_ctx* c, double lam) {
+  if (c->p.a_mode == LBM_A_FIXED) return c->p.a_fixed;
+  return 2.0 * c->p.a_beta * lam / (1.0 - c->p.alpha);
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, sizeof(d));
+  return d;
+}
+
+lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int32_t* ny,
+                       const double* dx, const double* u0, void* ws, void* stream,
+                       lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* m = check_params(p)) return fail(nullptr, LBM_EINVAL, m);
+  if (n < 1 || !nx || !ny) return fail(nullptr, LBM_EINVAL, "need at least one instance");
+  for (int i = 0; i < n; ++i)
+    if (nx[i] < 1 || ny[i] < 1) return fail(nullptr, LBM_EINVAL, "instance sizes must be >= 1");
+  if (!u0 || !ws) return fail(nullptr, LBM_EINVAL, "u0 and workspace must be device pointers");
+  if (((uintptr_t)ws) % kAlign) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (p->sponge > 0 && n > 1) return fail(nullptr, LBM_ENOTSUP, "sponge layers are single-instance only");
+
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->sc = make_scheme(p);
+  c->n_inst = n;
+  c->stream = (hipStream_t)stream;
+  c->lay = layout(p, n, nx, ny);
+  c->ws = (char*)ws;
+  c->slots = (Slots*)(c->ws + c->lay.slots);
+  c->insts_dev = (Inst*)(c->ws + c->lay.insts);
+  c->items_dev = (int*)(c->ws + c->lay.items);
+  c->insts.resize(n);
+  long long off = 0;
+  for (int i = 0; i < n; ++i) {
+    Inst& in = c->insts[i];
+    in.off = off;
+    in.nx = nx[i];
+    in.ny = ny[i];
+    in.dx = dx ? dx[i] : (n == 1 ? p->dx : 1.0 / nx[i]);
+    if (!(in.dx > 0.0)) {
+      delete c;
+      return fail(nullptr, LBM_EINVAL, "dx must be > 0");
+    }
+    off += (long long)nx[i] * ny[i];
+  }
+  c->plane = off;
+  if (n > 1) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    c->persistent_groups = cus * 4;
+  }
+  build_items(c);
+  lbm_status st = upload_tables(c);
+  if (st != LBM_OK) {
+    g_init_error = c->err;
+    delete c;
+    return st;
+  }
+  hipError_t e = vlbm::launch_fill_u32((unsigned int*)c->slots, 0u,
+                                       (long long)(sizeof(Slots) * n / 4), c->stream);
+  if (e == hipSuccess)
+    e = vlbm::launch_init(c->sc, c->insts.data(), n, c->insts_dev, c->plane, u0, c->cur(),
+                          c->slots, p->precision, c->stream);
+  if (e != hipSuccess) {
+    std::string m = std::string("init launch: ") + hipGetErrorString(e);
+    delete c;
+    return fail(nullptr, LBM_EDEVICE, m);
+  }
+  std::vector<Slots> h;
+  st = read_slots(c, h);
+  if (st != LBM_OK) {
+    g_init_error = c->err;
+    delete c;
+    return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (h[i].cnt[vlbm::CNT_BAD]) {
+      char buf[160];
+      snprintf(buf, sizeof(buf), "instance %d: %u cells of u0 are not admissible (rho <= 0 or p <= 0)",
+               i, h[i].cnt[vlbm::CNT_BAD]);
+      delete c;
+      return fail(nullptr, LBM_EPOSITIVITY, buf);
+    }
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (check_params(p)) return 0;
+  return layout(p, 1, &p->nx, &p->ny).total;
+}
+
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n, const int32_t* nx,
+                                 const int32_t* ny) {
+  if (check_params(p) || n < 1 || !nx || !ny) return 0;
+  for (int i = 0; i < n; ++i)
+    if (nx[i] < 1 || ny[i] < 1) return 0;
+  return layout(p, n, nx, ny).total;
+}
+
+lbm_status lbm_init(const lbm_params* p, const double* u0_dev, void* workspace_dev, void* stream,
+                    lbm_ctx** out) {
+  if (!p) return fail(nullptr, LBM_EINVAL, "params is NULL");
+  return common_init(p, 1, &p->nx, &p->ny, nullptr, u0_dev, workspace_dev, stream, out);
+}
+
+lbm_status lbm_init_batch(const lbm_params* p, int32_t n, const int32_t* nx, const int32_t* ny,
+                          const double* dx_host, const double* u0_packed_dev, void* workspace_dev,
+                          void* stream, lbm_ctx** out) {
+  return common_init(p, n, nx, ny, dx_host, u0_packed_dev, workspace_dev, stream, out);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t nsteps) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+  for (int32_t k = 0; k < nsteps; ++k) {
+    lbm_status s = launch_one(c);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return LBM_OK;
+  const auto key = std::make_tuple((int)nsteps, (int)(c->step % 3), (int)(c->step & 1));
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    const long long step0 = c->step;
+    lbm_status st = LBM_OK;
+    for (int32_t k = 0; k < nsteps && st == LBM_OK; ++k) st = launch_one(c);
+    c->step = step0;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    it = c->graphs.emplace(key, x).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+  c->step += nsteps;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_theta(lbm_ctx* c, double* tx, double* ty) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->n_inst != 1) return fail(c, LBM_ENOTSUP, "face output is single-instance only");
+  if (!tx || !ty) return fail(c, LBM_EINVAL, "theta buffers must be device pointers");
+  vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
+  a.theta_x = tx;
+  a.theta_y = ty;
+  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  c->step += 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
+  if (!out) return fail(c, LBM_EINVAL, "output must be a device pointer");
+  hipError_t e = vlbm::launch_moments(c->insts[inst], c->plane, c->cur(), out, c->p.precision,
+                                      c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "moments launch");
+  std::vector<Slots> h;
+  lbm_status st = read_slots(c, h);
+  if (st != LBM_OK) return st;
+  lbm_status res = LBM_OK;
+  unsigned bad = 0, guard = 0, bouchut = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    bad += h[i].cnt[vlbm::CNT_BAD];
+    guard += h[i].cnt[vlbm::CNT_GUARD];
+    bouchut |= h[i].cnt[vlbm::CNT_BOUCHUT];
+  }
+  char buf[160];
+  if (bad) {
+    snprintf(buf, sizeof(buf), "%u non-admissible cells were produced", bad);
+    res = fail(c, LBM_EPOSITIVITY, buf);
+  } else if (guard) {
+    snprintf(buf, sizeof(buf), "%u face states left the admissible set", guard);
+    res = fail(c, LBM_EGUARD, buf);
+  } else if (bouchut) {
+    res = fail(c, LBM_EBOUCHUT, "the fixed kinetic speed fell below the Bouchut bound");
+  }
+  if (bad || guard || bouchut) {
+    for (auto& s : h) s.cnt[0] = s.cnt[1] = s.cnt[2] = s.cnt[3] = 0;
+    st = write_slots(c, h);
+    if (st != LBM_OK) return st;
+  } else {
+    // the limited-face counter is cleared too
+    bool any = false;
+    for (auto& s : h) {
+      any |= s.cnt[vlbm::CNT_LIMITED] != 0;
+      s.cnt[vlbm::CNT_LIMITED] = 0;
+    }
+    if (any) {
+      st = write_slots(c, h);
+      if (st != LBM_OK) return st;
+    }
+  }
+  return res;
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, int32_t inst, lbm_diag* d) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (inst < 0 || inst >= c->n_inst || !d) return fail(c, LBM_EINVAL, "bad instance or output");
+  std::vector<Slots> h;
+  lbm_status st = read_slots(c, h);
+  if (st != LBM_OK) return st;
+  const Slots& s = h[inst];
+  const int slot = (int)(c->step % 3);
+  d->lambda = bits_to_double(s.lam[slot]);
+  d->a = host_kinetic_speed(c, d->lambda);
+  d->t = s.t[slot];
+  d->step = c->step;
+  d->n_guard = s.cnt[vlbm::CNT_GUARD];
+  d->n_limited = s.cnt[vlbm::CNT_LIMITED];
+  d->n_bad = s.cnt[vlbm::CNT_BAD];
+  d->bouchut = (int32_t)s.cnt[vlbm::CNT_BOUCHUT];
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  return (size_t)20 * (size_t)c->plane * c->elem();
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!dst) return fail(c, LBM_EINVAL, "destination must be a device pointer");
+  hipError_t e = hipMemcpyAsync(dst, c->cur(), lbm_state_bytes(c), hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "get_state copy");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* src) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!src) return fail(c, LBM_EINVAL, "source must be a device pointer");
+  hipError_t e = hipMemcpyAsync(c->cur(), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
+  const int slot = (int)(c->step % 3);
+  for (int i = 0; i < c->n_inst && e == hipSuccess; ++i)
+    e = vlbm::launch_fill_u32((unsigned int*)&c->slots[i].lam[slot], 0u, 2, c->stream);
+  if (e == hipSuccess)
+    e = vlbm::launch_lambda_state(c->sc, c->insts.data(), c->n_inst, c->plane, c->cur(),
+                                  c->slots, slot, c->p.precision, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "set_state wavespeed");
+  return LBM_OK;
+}
+
+lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double* Ub1, double* Ub0);
+lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const double* Ub0, double* u0b);
+
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t rows, int32_t waves) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (rows != 0 && (rows < kMinStripRows || rows > 4096))
+    return fail(c, LBM_EINVAL, "strip rows must lie in [16, 4096]");
+  if (waves != 0 && (waves < 1 || waves > 4)) return fail(c, LBM_EINVAL, "waves per group must lie in [1, 4]");
+  if (rows) c->strip_rows = rows;
+  if (waves) c->waves = waves;
+  build_items(c);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return upload_tables(c);
+}
+
+lbm_status lbm_get_launch(const lbm_ctx* c, int32_t* rows, int32_t* waves) {
+  if (!c || !rows || !waves) return LBM_EINVAL;
+  *rows = c->strip_rows;
+  *waves = c->waves;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  char key[160];
+  long long cells = c->plane;
+  snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d", c->n_inst, c->insts[0].nx,
+           c->insts[0].ny, cells, c->p.precision, c->p.limiters, c->p.order);
+  // cache lookup: a flat JSON object {"key": [rows, waves], ...}
+  std::string text;
+  if (path) {
+    FILE* f = fopen(path, "rb");
+    if (f) {
+      char b[4096];
+      size_t r;
+      while ((r = fread(b, 1, sizeof(b), f)) > 0) text.append(b, r);
+      fclose(f);
+      const std::string k = std::string("\"") + key + "\"";
+      size_t pos = text.find(k);
+      if (pos != std::string::npos) {
+        int rows = 0, waves = 0;
+        if (sscanf(text.c_str() + pos + k.size(), " : [ %d , %d ]", &rows, &waves) == 2)
+          return lbm_set_launch(c, rows, waves);
+      }
+    }
+  }
+  std::vector<Slots> saved;
+  lbm_status st = read_slots(c, saved);
+  if (st != LBM_OK) return st;
+  const int rows_c[] = {16, 32, 64, 128, 256};
+  const int waves_c[] = {1, 2, 4};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, LBM_EDEVICE, "hipEventCreate");
+  float best = 1e30f;
+  int best_r = c->strip_rows, best_w = c->waves;
+  for (int r : rows_c) {
+    if (r > 4 * c->insts[0].ny && r != 16) continue;
+    for (int w : waves_c) {
+      st = lbm_set_launch(c, r, w);
+      if (st != LBM_OK) break;
+      // time launches that all read the current state and write the other
+      // buffer (the state is not advanced)
+      vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
+      const int reps = 4;
+      hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) e = vlbm::launch_step(a, c->p.precision, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return hip_fail(c, e, "autotune");
+      }
+      if (ms < best) {
+        best = ms;
+        best_r = r;
+        best_w = w;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st = write_slots(c, saved);
+  if (st != LBM_OK) return st;
+  st = lbm_set_launch(c, best_r, best_w);
+  if (st != LBM_OK) return st;
+  if (path) {
+    // append the entry to the flat JSON object
+    std::string body = text;
+    size_t end = body.rfind('}');
+    char entry[256];
+    snprintf(entry, sizeof(entry), "\"%s\": [%d, %d]", key, best_r, best_w);
+    if (end == std::string::npos) {
+      body = std::string("{\n  ") + entry + "\n}\n";
+    } else {
+      std::string head = body.substr(0, end);
+      bool empty = head.find('"') == std::string::npos;
+      while (!head.empty() && (head.back() == '\n' || head.back() == ' ')) head.pop_back();
+      body = head + (empty ? "\n  " : ",\n  ") + entry + "\n}\n";
+    }
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, LBM_EINVAL, "cannot write the autotune cache file");
+    fwrite(body.data(), 1, body.size(), f);
+    fclose(f);
+  }
+  return LBM_OK;
+}
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOTSUP: return "not supported";
+    case LBM_EDEVICE: return "device error";
+    case LBM_EPOSITIVITY: return "non-admissible state";
+    case LBM_ENONFINITE: return "non-finite value";
+    case LBM_EBOUCHUT: return "Bouchut condition violated";
+    case LBM_EGUARD: return "face state outside the admissible set";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+  if (!c) return g_init_error.c_str();
+  return c->err.c_str();
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- adjoint entry points
+extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double* Ub1,
+                                       double* Ub0) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->n_inst != 1 || c->p.precision != LBM_FP64)
+    return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (c->p.bc_x != LBM_BC_PERIODIC || c->p.bc_y != LBM_BC_PERIODIC)
+    return fail(c, LBM_ENOTSUP, "the adjoint supports periodic boundaries only");
+  if (c->p.sponge > 0) return fail(c, LBM_ENOTSUP, "the adjoint does not support sponge layers");
+  if (!U || !Ub1 || !Ub0) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
+  if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
+  if ((const void*)U == c->other() || (const void*)U == c->cur())
+    return fail(c, LBM_EINVAL, "U_n must not be one of the context's own state buffers");
+  const Inst& in = c->insts[0];
+  double* tx = (double*)(c->ws + c->lay.theta);
+  double* ty = tx + (size_t)(in.nx + 1) * in.ny;
+  // lambda^n of U (scratch slot: a second Slots record is not available, so
+  // use the slot that the next forward step would clear)
+  const int scratch = (int)((c->step + 2) % 3);
+  hipError_t e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
+  if (e == hipSuccess)
+    e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, c->plane, U, c->slots, scratch,
+                                  LBM_FP64, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
+  // theta^n of U with the forward kernel (its state output goes to the
+  // context's other buffer, which the next forward step overwrites anyway;
+  // the counters it adds are restored below)
+  std::vector<Slots> saved;
+  lbm_status st = read_slots(c, saved);
+  if (st != LBM_OK) return st;
+  vlbm::StepArgs a = make_args(c, U, c->other(), scratch);
+  a.theta_x = tx;
+  a.theta_y = ty;
+  e = vlbm::launch_step(a, LBM_FP64, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint theta");
+  e = vlbm::launch_adjoint_step(c->sc, in, c->plane, U, Ub1, Ub0, tx, ty, c->slots, scratch,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+  // restore the scalar slots (lambda, t, counters) of the forward run
+  return write_slots(c, saved);
+}
+
+extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const double* Ub0,
+                                       double* u0b) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->n_inst != 1 || c->p.precision != LBM_FP64)
+    return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (!u0 || !Ub0 || !u0b) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
+  std::vector<Slots> saved;
+  lbm_status st = read_slots(c, saved);
+  if (st != LBM_OK) return st;
+  // lambda^0 of u0 into a scratch slot
+  const int scratch = (int)((c->step + 2) % 3);
+  hipError_t e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
+  if (e == hipSuccess)
+    e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, (long long)c->insts[0].nx * c->insts[0].ny,
+                                  u0, c->slots, scratch, LBM_FP64, c->stream);
+  if (e == hipSuccess)
+    e = vlbm::launch_adjoint_init(c->sc, c->insts[0], u0, Ub0, u0b, c->slots, scratch, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "init adjoint launch");
+  return write_slots(c, saved);
+}

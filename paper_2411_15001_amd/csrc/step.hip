@@ -1,0 +1,600 @@
+// Fused collide-limit-stream step of the blended D2Q5 vectorial lattice
+// Boltzmann scheme (Wissocq, Liu, Abgrall), gfx950.
+//
+// Work decomposition.  A wave owns a strip of 64 consecutive columns and H
+// consecutive rows of one instance and marches up the strip one row at a
+// time; lane l holds column x0 + l.  x-neighbours are exchanged with
+// wave-wide lane shifts; y-neighbours are the rows the lane already holds in
+// registers from the previous iterations.  No LDS and no barrier is used.
+// The blending factor of an x-face i+1/2 needs the density bounds of cells i
+// and i+1, which need the face states of their own faces, so the LMP variant
+// has a halo of R = 2 lanes on each side (60 output columns per wave) and the
+// other variants R = 1 (62 columns).  Along y the march runs two rows ahead
+// of the row it completes (the same dependency), so a strip reads H + 4 rows.
+//
+// Pipeline of one iteration (newest row L loaded):
+//   row L     : Maxwellians and d_k (Example 1), x-face state u*_{i+1/2} and
+//               Delta F_{i+1/2} (eqs. (12), (22)), y-face L-1/2 (u*, Delta G);
+//   row L - 1 : density bounds (eq. (29)), theta of its x-face i+1/2 and of
+//               the y-face L-3/2 (Sections 3.3, 3.4), streamed distributions
+//               u_1, u_2 (eq. (25)) and u_3, and the moment sum of eq. (27)
+//               up to its face L-3/2;
+//   row L - 2 : last face term of eq. (27) and u_4; the row is complete.
+// Each cell's moment update adds, in this order, alpha u and the terms of its
+// faces i-1/2, i+1/2, j-1/2, j+1/2 (incoming distribution minus theta times
+// its own distribution leaving through that face): the evaluation order of
+// the oracle, so the FP64 path reproduces it bit for bit.
+//
+// The wavespeed of every new cell (Section 4 preamble) is reduced over the
+// wave with lane shuffles and merged with one 64-bit atomic max per strip
+// into the instance's next lambda slot; the next launch derives a^{n+1} from
+// it on the device.
+
+#include <math.h>
+
+#include "vlbm_internal.h"
+
+namespace vlbm {
+namespace {
+
+constexpr double kHuge = __builtin_huge_val();
+
+template <class X>
+__device__ __forceinline__ X vmin(X a, X b) { return (b < a) ? b : a; }
+template <class X>
+__device__ __forceinline__ X vmax(X a, X b) { return (b > a) ? b : a; }
+
+// value held by lane - 1 / lane + 1 (own value at the wave ends)
+template <class X>
+__device__ __forceinline__ X from_left(X v) { return __shfl_up(v, 1u, 64); }
+template <class X>
+__device__ __forceinline__ X from_right(X v) { return __shfl_down(v, 1u, 64); }
+
+__device__ __forceinline__ int map_index(int i, int n, int bc) {
+  if (bc == 0) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ bool in_sponge(const Scheme& s, int i, int j, int nx, int ny) {
+  const int w = s.sponge;
+  if (s.bc_x == 1 && (i < w || i >= nx - w)) return true;
+  if (s.bc_y == 1 && (j < w || j >= ny - w)) return true;
+  return false;
+}
+
+// Section 3.3.3
+__device__ __forceinline__ double theta_rho_pp(double rs, double D, double kappa, double eps) {
+  if (D == 0.0) return kHuge;
+  const double t = kappa * rs / fabs(D) - eps;
+  return vmax(0.0, t);
+}
+
+// Section 3.3.1, final case formula (L = left/bottom cell, R = right/top cell)
+__device__ __forceinline__ double theta_rho_lmp(double rs, double D, double kappa, double muL,
+                                                double nuL, double muR, double nuR) {
+  if (D == 0.0) return 1.0;
+  if (D > 0.0) return kappa * vmin(nuR - rs, rs - muL) / D;
+  return -kappa * vmin(rs - muR, nuL - rs) / D;
+}
+
+// Section 3.4: kappa over the spectral radius of B^{-1/2} A B^{-1/2}
+__device__ __forceinline__ double theta_p(double r0, double m1, double m2, double E, double Dr,
+                                          double Dm1, double Dm2, double DE, double kappa,
+                                          double eps) {
+  const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
+  const double g1 = 2.0 * (Dr * E + DE * r0 - Dm1 * m1 - Dm2 * m2);
+  const double g2 = Dm1 * Dm1 + Dm2 * Dm2 - 2.0 * Dr * DE;
+  double disc = g1 * g1 - 4.0 * g0 * g2;
+  disc = vmax(0.0, disc);
+  const double e1 = fabs(Dr) / r0;
+  const double e2 = (fabs(g1) + sqrt(disc)) / (-2.0 * g0);
+  const double r = vmax(e1, e2);
+  if (r == 0.0) return kHuge;
+  return vmax(0.0, kappa / r - eps);
+}
+
+// theta = min(1, selected theta^rho, theta^p) of one face (Section 3.2).  A
+// face state outside the admissible set takes the first-order value 0.
+template <class C>
+__device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], const C dF[4],
+                                             double kappa, C muL, C nuL, C muR, C nuR,
+                                             int& guard) {
+  guard = 0;
+  if (s.order == 1) return 0.0;
+  if (s.limiters == 0) return 1.0;
+  const double r0 = us[0], m1 = us[1], m2 = us[2], E = us[3];
+  const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
+  if (!(r0 > 0.0) || !(g0 < 0.0)) {
+    guard = 1;
+    return 0.0;
+  }
+  const double D = dF[0];
+  double t = 1.0;
+  if (s.limiters & 1u) t = vmin(t, theta_rho_pp(r0, D, kappa, s.eps));
+  if (s.limiters & 2u)
+    t = vmin(t, theta_rho_lmp(r0, D, kappa, (double)muL, (double)nuL, (double)muR, (double)nuR));
+  if (s.limiters & 4u)
+    t = vmin(t, theta_rho_lmp(r0, D, kappa, s.rlmp_lo * (double)muL, s.rlmp_hi * (double)nuL,
+                              s.rlmp_lo * (double)muR, s.rlmp_hi * (double)nuR));
+  if (s.limiters & 8u)
+    t = vmin(t, theta_p(r0, m1, m2, E, D, (double)dF[1], (double)dF[2], (double)dF[3], kappa,
+                        s.eps));
+  return t;
+}
+
+// Wavespeed |v| + sqrt(gamma p / rho) of one state, or -1 if it is not
+// admissible (rho <= 0, p <= 0 or a non-finite result).
+__device__ __forceinline__ double cell_wavespeed(double rho, double m1, double m2, double E,
+                                                 double gamma) {
+  const double ir = 1.0 / rho;
+  const double v1 = m1 * ir;
+  const double v2 = m2 * ir;
+  const double ke = 0.5 * (m1 * v1 + m2 * v2);
+  const double p = (gamma - 1.0) * (E - ke);
+  const double l = sqrt(v1 * v1 + v2 * v2) + sqrt(gamma * p * ir);
+  if (!(rho > 0.0) || !(p > 0.0) || !(l <= 1.79769313486231570e308)) return -1.0;
+  return l;
+}
+
+// Euler fluxes (Section 1) of one state.
+template <class C>
+__device__ __forceinline__ void fluxes(const C u[4], C gm1, C f[4], C g[4]) {
+  const C rho = u[0], m1 = u[1], m2 = u[2], E = u[3];
+  const C ir = C(1.0) / rho;
+  const C v1 = m1 * ir;
+  const C v2 = m2 * ir;
+  const C ke = C(0.5) * (m1 * v1 + m2 * v2);
+  const C p = gm1 * (E - ke);
+  f[0] = m1;
+  f[1] = m1 * v1 + p;
+  f[2] = m2 * v1;
+  f[3] = (E + p) * v1;
+  g[0] = m2;
+  g[1] = m1 * v2;
+  g[2] = m2 * v2 + p;
+  g[3] = (E + p) * v2;
+}
+
+// Maxwellians of Example 1, k = 0..3 for M_1..M_4: w u +- flux / (2a).
+template <class C>
+__device__ __forceinline__ C maxw(int k, C u, C f, C g, C w, C r2a) {
+  const C wu = w * u;
+  switch (k) {
+    case 0: return wu + f * r2a;
+    case 1: return wu - f * r2a;
+    case 2: return wu + g * r2a;
+    default: return wu - g * r2a;
+  }
+}
+
+template <class T, class C>
+struct StepConst {
+  double a, kappa, klim, lam;
+  C w, r2a, r2k, ac, alpha, gm1;
+};
+
+template <class T, class C>
+__device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double lam) {
+  StepConst<T, C> k;
+  k.lam = lam;
+  k.a = (s.a_mode == 1) ? s.a_fixed : 2.0 * s.beta * lam / (1.0 - s.alpha);
+  k.kappa = 0.5 * k.a * (1.0 - s.alpha);
+  k.klim = k.kappa * (1.0 - s.theta_margin);
+  k.w = (C)(0.25 * (1.0 - s.alpha));
+  k.r2a = (C)(1.0 / (2.0 * k.a));
+  k.r2k = (C)(1.0 / (2.0 * k.kappa));
+  k.ac = (C)k.a;
+  k.alpha = (C)s.alpha;
+  k.gm1 = (C)(s.gamma - 1.0);
+  return k;
+}
+
+// One strip: columns x0 .. x0 + 63, output rows [y0, y1).
+template <class T, class C, bool LMP>
+__device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* sl, int xs, int ys,
+                                      int lane) {
+  constexpr int R = LMP ? 2 : 1;
+  constexpr int OW = 64 - 2 * R;
+  const Scheme& sc = A.sc;
+  const int nx = in.nx, ny = in.ny;
+  const int x0 = xs * OW - R;
+  const int gi = x0 + lane;
+  const int ci = map_index(gi, nx, sc.bc_x);
+  const bool lane_out = lane >= R && lane < 64 - R && gi < nx;
+  const bool right_out = lane + 1 >= R && lane + 1 < 64 - R && gi + 1 < nx && gi + 1 >= 0;
+  const int y0 = ys * A.strip_h;
+  const int y1 = min(y0 + A.strip_h, ny);
+  const bool sponge = sc.sponge > 0;
+
+  const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+  const StepConst<T, C> K = step_const<T, C>(sc, lam);
+
+  if (xs == 0 && ys == 0 && lane == 0) {
+    // rotate the scalar slots (this instance's first strip does it)
+    sl->lam[(A.slot + 2) % 3] = 0ull;
+    sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
+  }
+
+  const T* __restrict__ src = (const T*)A.src + in.off + ci;
+  T* __restrict__ dst = (T*)A.dst + in.off + gi;
+  const long long P = A.plane;
+
+  // carried state (zero before the first rows arrive)
+  C pu[4] = {}, pf[4] = {}, pg[4] = {}, puk[4][4] = {};  // row L - 1
+  C pusx[4] = {}, pdF[4] = {};                          // x-face i+1/2 of row L - 1
+  C pusy[4] = {}, pdG[4] = {};                          // y-face L - 3/2
+  C pmu = C(0), pnu = C(0);                             // bounds of row L - 2
+  C qM3[4] = {}, qd3[4] = {}, qP[4] = {};               // row L - 2
+
+  double lmax = 0.0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0;
+
+  T raw[20];
+  {
+    const int cj = map_index(y0 - 2, ny, sc.bc_y);
+    const T* s = src + (long long)cj * nx;
+#pragma unroll
+    for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+  }
+
+  for (int L = y0 - 2; L <= y1 + 1; ++L) {
+    C u[4], uk[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (C)raw[c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) uk[k][c] = (C)raw[4 + 4 * k + c];
+    if (L <= y1) {  // prefetch row L + 1
+      const int cj = map_index(L + 1, ny, sc.bc_y);
+      const T* s = src + (long long)cj * nx;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    }
+
+    // ---- row L: fluxes, Maxwellians, faces
+    C f[4], g[4];
+    fluxes(u, K.gm1, f, g);
+    C usx[4], dF[4], usy[4], dG[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C d1 = maxw(0, u[c], f[c], g[c], K.w, K.r2a) - uk[0][c];
+      const C d2 = maxw(1, u[c], f[c], g[c], K.w, K.r2a) - uk[1][c];
+      const C d4 = maxw(3, u[c], f[c], g[c], K.w, K.r2a) - uk[3][c];
+      const C uE = from_right(u[c]);
+      const C fE = from_right(f[c]);
+      const C d2E = from_right(d2);
+      usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
+      dF[c] = K.ac * (d1 - d2E);
+      const C pd3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a) - puk[2][c];
+      usy[c] = C(0.5) * (pu[c] + u[c]) - (g[c] - pg[c]) * K.r2k;
+      dG[c] = K.ac * (pd3 - d4);
+    }
+
+    // ---- row L - 1: density bounds (eq. (29)), faces' theta
+    C mu1 = C(0), nu1 = C(0);
+    if (LMP) {
+      const C rW = from_left(pusx[0]);
+      C lo = pu[0], hi = pu[0];
+      lo = vmin(lo, rW);
+      hi = vmax(hi, rW);
+      lo = vmin(lo, pusx[0]);
+      hi = vmax(hi, pusx[0]);
+      lo = vmin(lo, pusy[0]);
+      hi = vmax(hi, pusy[0]);
+      lo = vmin(lo, usy[0]);
+      hi = vmax(hi, usy[0]);
+      mu1 = lo;
+      nu1 = hi;
+    }
+    const C muE = from_right(mu1);
+    const C nuE = from_right(nu1);
+    int gx, gy;
+    double thx = face_theta(sc, pusx, pdF, K.klim, mu1, nu1, muE, nuE, gx);
+    double thy = face_theta(sc, pusy, pdG, K.klim, pmu, pnu, mu1, nu1, gy);
+    if (sponge) {
+      if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi + 1, L - 1, nx, ny)) thx = 0.0;
+      if (in_sponge(sc, gi, L - 2, nx, ny) || in_sponge(sc, gi, L - 1, nx, ny)) thy = 0.0;
+    }
+    const bool row1 = L - 1 >= y0 && L - 1 < y1;  // row L - 1 is produced by this strip
+    const bool row2 = L - 2 >= y0 && L - 2 < y1;  // row L - 2 is completed now
+    if (row1 && right_out) {
+      n_guard += gx;
+      n_lim += (thx < 1.0);
+    }
+    if (row1 && lane_out) {
+      n_guard += gy;
+      n_lim += (thy < 1.0);
+    }
+    if (A.theta_x) {
+      const int fi = gi + 1;
+      if (row1 && (lane_out || right_out) && fi >= 0 && fi <= nx)
+        A.theta_x[(long long)(L - 1) * (nx + 1) + fi] = thx;
+      if (lane_out && (row1 || row2) && L - 1 >= 0 && L - 1 <= ny)
+        A.theta_y[(long long)(L - 1) * nx + gi] = thy;
+    }
+
+    // ---- rows L - 1 and L - 2: streaming and the moment slot (eqs. (25), (27))
+    const C tR = (C)thx;
+    const C tL = from_left(tR);
+    const C tB = (C)thy;
+    C fin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C pM1 = maxw(0, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pM2 = maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pM3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pM4 = maxw(3, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pd1 = pM1 - puk[0][c];
+      const C pd2 = pM2 - puk[1][c];
+      const C pd4 = pM4 - puk[3][c];
+      const C M1W = from_left(pM1);
+      const C d1W = from_left(pd1);
+      const C M2E = from_right(pM2);
+      const C d2E = from_right(pd2);
+      // row L - 1: faces i-1/2, i+1/2 and j-1/2 (= L - 3/2)
+      const C u1n = M1W + tL * d1W;
+      const C u2n = M2E + tR * d2E;
+      const C u3n = qM3[c] + tB * qd3[c];
+      C s = K.alpha * pu[c];
+      s = s + (u1n - tL * pd2);
+      s = s + (u2n - tR * pd1);
+      s = s + (u3n - tB * pd4);
+      // row L - 2 completes with its face j+1/2 (= L - 3/2)
+      const C u4n = pM4 + tB * pd4;
+      fin[c] = qP[c] + (u4n - tB * qd3[c]);
+      if (row1 && lane_out) {
+        const long long o = (long long)(L - 1) * nx;
+        dst[o + (4 + c) * P] = (T)u1n;
+        dst[o + (8 + c) * P] = (T)u2n;
+        dst[o + (12 + c) * P] = (T)u3n;
+      }
+      if (row2 && lane_out) {
+        const long long o = (long long)(L - 2) * nx;
+        dst[o + c * P] = (T)fin[c];
+        dst[o + (16 + c) * P] = (T)u4n;
+      }
+      qP[c] = s;
+      qM3[c] = pM3;
+      qd3[c] = pM3 - puk[2][c];
+    }
+    if (row2 && lane_out) {
+      // wavespeed of the stored new state, in float64
+      const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
+                                      (double)(T)fin[3], sc.gamma);
+      if (l < 0.0)
+        n_bad += 1;
+      else
+        lmax = vmax(lmax, l);
+    }
+    pmu = mu1;
+    pnu = nu1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      pu[c] = u[c];
+      pf[c] = f[c];
+      pg[c] = g[c];
+      pusx[c] = usx[c];
+      pdF[c] = dF[c];
+      pusy[c] = usy[c];
+      pdG[c] = dG[c];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
+    }
+  }
+
+  // ---- wave reductions and one atomic per strip
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_bad += __shfl_xor(n_bad, off, 64);
+    n_guard += __shfl_xor(n_guard, off, 64);
+    n_lim += __shfl_xor(n_lim, off, 64);
+  }
+  if (lane == 0) {
+    atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
+    if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
+    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
+    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+  }
+}
+
+template <class T, class C, bool LMP>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int grp = blockIdx.x;
+  if (A.xcd_remap && (A.groups & 7) == 0) {
+    // groups are dispatched round-robin over the 8 XCDs: give each XCD one
+    // contiguous range of strips so that neighbouring strips share its L2
+    const int per = A.groups >> 3;
+    grp = (grp & 7) * per + (grp >> 3);
+  }
+  const long long total = (long long)A.groups * A.waves_per_group;
+  for (long long item = (long long)grp * A.waves_per_group + wave; item < A.n_items;
+       item += total) {
+    int ii = 0;
+    Inst in;
+    if (A.n_inst == 1) {
+      in = A.inst0;
+    } else {
+      ii = A.item_inst[item];
+      in = A.insts[ii];
+    }
+    const long long local = item - in.item0;
+    const int xs = (int)(local % in.xs);
+    const int ys = (int)(local / in.xs);
+    march<T, C, LMP>(A, in, A.slots + ii, xs, ys, lane);
+  }
+}
+
+// ---------------------------------------------------------------- init etc.
+
+// Wavespeed maximum of a moment field (4 planes of Src values, rounded to the
+// storage type T first) into slots[slot]; counts non-admissible cells.
+template <class Src, class T>
+__global__ __launch_bounds__(256) void lambda_kernel(const Src* __restrict__ u, long long plane,
+                                                     long long n, double gamma, Slots* sl,
+                                                     int slot) {
+  double lmax = 0.0;
+  unsigned bad = 0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double r = (double)(T)u[c], m1 = (double)(T)u[plane + c],
+                 m2 = (double)(T)u[2 * plane + c], E = (double)(T)u[3 * plane + c];
+    const double l = cell_wavespeed(r, m1, m2, E, gamma);
+    if (l < 0.0)
+      bad += 1;
+    else
+      lmax = vmax(lmax, l);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    bad += __shfl_xor(bad, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sl->lam[slot], (unsigned long long)__double_as_longlong(lmax));
+    if (bad) atomicAdd(&sl->cnt[CNT_BAD], bad);
+  }
+}
+
+// u_k^0 = M_k(u0; a^0) (Section 4 preamble), moment slot = u0.
+template <class T, class C>
+__global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ u0, long long n,
+                                                   T* __restrict__ S, long long plane, Scheme sc,
+                                                   const Slots* sl) {
+  const double lam = __longlong_as_double((long long)sl->lam[0]);
+  const StepConst<T, C> K = step_const<T, C>(sc, lam);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    C u[4], f[4], g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = (C)(T)u0[k * n + c];
+    fluxes(u, K.gm1, f, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S[k * plane + c] = (T)u[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S[(4 + 4 * q + k) * plane + c] = (T)maxw(q, u[k], f[k], g[k], K.w, K.r2a);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void moments_kernel(const T* __restrict__ S, long long plane,
+                                                      long long n, double* __restrict__ out) {
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k * n + c] = (double)S[k * plane + c];
+  }
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, unsigned int v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* p, double v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int grid_for(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
+  const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
+  const dim3 block(64 * a.waves_per_group);
+  const dim3 grid(a.groups);
+  if (precision == 0) {
+    if (lmp)
+      hipLaunchKernelGGL((step_kernel<double, double, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((step_kernel<double, double, false>), grid, block, 0, s, a);
+  } else {
+    if (lmp)
+      hipLaunchKernelGGL((step_kernel<float, float, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((step_kernel<float, float, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const Scheme& sc, const Inst* insts, int n_inst, const Inst* /*dev*/,
+                       long long plane, const double* u0, void* S, Slots* slots, int precision,
+                       hipStream_t s) {
+  long long u0_off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const Inst& in = insts[i];
+    const long long n = (long long)in.nx * in.ny;
+    const double* u = u0 + u0_off;
+    if (precision == 0)
+      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u,
+                         n, n, sc.gamma, slots + i, 0);
+    else
+      hipLaunchKernelGGL((lambda_kernel<double, float>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
+                         n, sc.gamma, slots + i, 0);
+    if (precision == 0)
+      hipLaunchKernelGGL((init_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
+                         (double*)S + in.off, plane, sc, (const Slots*)(slots + i));
+    else
+      hipLaunchKernelGGL((init_kernel<float, float>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
+                         (float*)S + in.off, plane, sc, (const Slots*)(slots + i));
+    u0_off += 4 * n;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts, int n_inst, long long plane,
+                               const void* S, Slots* slots, int slot, int precision,
+                               hipStream_t s) {
+  for (int i = 0; i < n_inst; ++i) {
+    const Inst& in = insts[i];
+    const long long n = (long long)in.nx * in.ny;
+    if (precision == 0)
+      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s,
+                         (const double*)S + in.off, plane, n, sc.gamma, slots + i, slot);
+    else
+      hipLaunchKernelGGL((lambda_kernel<float, float>), dim3(grid_for(n)), dim3(256), 0, s,
+                         (const float*)S + in.off, plane, n, sc.gamma, slots + i, slot);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Inst& in, long long plane, const void* S, double* out,
+                          int precision, hipStream_t s) {
+  const long long n = (long long)in.nx * in.ny;
+  if (precision == 0)
+    hipLaunchKernelGGL((moments_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s,
+                       (const double*)S + in.off, plane, n, out);
+  else
+    hipLaunchKernelGGL((moments_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s,
+                       (const float*)S + in.off, plane, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm

@@ -1,0 +1,74 @@
+// Internal declarations shared by the kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vlbm {
+
+// Scheme parameters shared by every instance of a context.
+struct Scheme {
+  double gamma, alpha, beta, a_fixed, eps, rlmp_lo, rlmp_hi, theta_margin;
+  int a_mode, order, limiters, bc_x, bc_y, sponge;
+};
+
+// One problem instance inside the state buffers.
+struct Inst {
+  long long off;   // element offset of cell (0, 0) inside every plane
+  long long item0; // first work item (strip) of this instance
+  double dx;
+  int nx, ny;
+  int xs, ys;      // strips along x and y
+};
+
+// Per-instance device scalars.  lam and t rotate over three slots: step n
+// reads slot n % 3, writes slot (n + 1) % 3 and clears slot (n + 2) % 3.
+struct alignas(128) Slots {
+  unsigned long long lam[3]; // bit patterns of non-negative doubles
+  double t[3];
+  unsigned int cnt[4];       // guard, limited, bad, bouchut (cumulative)
+};
+enum { CNT_GUARD = 0, CNT_LIMITED = 1, CNT_BAD = 2, CNT_BOUCHUT = 3 };
+
+struct StepArgs {
+  const void* src;
+  void* dst;
+  long long plane;        // elements per plane (sum of all instances' cells)
+  Slots* slots;           // [n_inst]
+  const Inst* insts;      // [n_inst], device memory
+  const int* item_inst;   // [n_items] instance of every item (batches), or null
+  Inst inst0;             // the instance when n_inst == 1
+  long long n_items;
+  int n_inst;
+  int slot;               // step index mod 3
+  int strip_h;            // rows per strip
+  int waves_per_group;
+  int xcd_remap;          // map consecutive groups onto one XCD
+  int groups;             // launched workgroups
+  double* theta_x;        // optional face output (single instance)
+  double* theta_y;
+  Scheme sc;
+};
+
+// Launchers (step.hip).
+hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s);
+hipError_t launch_init(const Scheme& sc, const Inst* insts_host, int n_inst,
+                       const Inst* insts_dev, long long plane, const double* u0,
+                       void* S, Slots* slots, int precision, hipStream_t s);
+hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_inst,
+                               long long plane, const void* S, Slots* slots,
+                               int slot, int precision, hipStream_t s);
+hipError_t launch_moments(const Inst& in, long long plane, const void* S,
+                          double* out, int precision, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s);
+// Adjoint (adjoint.hip).
+hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane,
+                               const double* U, const double* Ubar1, double* Ubar0,
+                               const double* theta_x, const double* theta_y,
+                               const Slots* slot_src, int slot, hipStream_t s);
+hipError_t launch_adjoint_init(const Scheme& sc, const Inst& in, const double* u0,
+                               const double* Ubar0, double* u0bar,
+                               const Slots* slots, int slot, hipStream_t s);
+
+}  // namespace vlbm

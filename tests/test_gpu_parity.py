@@ -1,0 +1,262 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+The float64 kernel evaluates every expression in the oracle's order without
+contraction, so states and face factors are compared bit for bit; the 1e-11
+bound on the per-plane relative error is the acceptance bar."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_15001_amd import binding as B
+from paper_2411_15001_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.lib()
+    return torch
+
+
+def Solver(*a, **k):
+    from paper_2411_15001_amd.solver import Solver as S
+
+    return S(*a, **k)
+
+
+def rel_err(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)[:, None]
+    return float(np.max(np.abs(a - b) / scale))
+
+
+def okw(ocfg):
+    """lbm_params keywords matching an oracle Config."""
+    return dict(dx=ocfg.params().dx, gamma=ocfg.gamma, alpha=ocfg.alpha, order=ocfg.order,
+                limiters=ocfg.limiters, a_mode=ocfg.a_mode, a_beta=ocfg.a_beta,
+                a_fixed=ocfg.a_fixed, bc_x=ocfg.bc_x, bc_y=ocfg.bc_y, sponge=ocfg.sponge,
+                eps=ocfg.eps, rlmp_lo=ocfg.rlmp_lo, rlmp_hi=ocfg.rlmp_hi)
+
+
+def test_c0_four_quadrant_parity():
+    """64x64 four-quadrant problems, seeds 0-9, outflow, alpha = 1/2,
+    a^n = 4.4 lambda^n, PP + pressure, 100 steps: full state within 1e-11 and
+    bit-identical."""
+    n, steps = 64, 100
+    for seed in range(10):
+        print("c0 seed", seed, flush=True)
+        u0 = cases.riemann4(n, seed=seed)
+        ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+        S, _ = oracle.init(ocfg, u0)
+        S, t_ref, info, _ = oracle.run(ocfg, S, steps)
+        s = Solver(u0, **okw(ocfg))
+        s.step(steps)
+        G = s.get_state().cpu().numpy()
+        d = s.diagnostics()
+        s.moments()
+        assert rel_err(G, S) <= 1e-11
+        assert np.array_equal(G, S), "seed %d: max rel err %.3e" % (seed, rel_err(G, S))
+        assert d["lam"] == info.lambda_new
+        assert abs(d["t"] - t_ref) <= 1e-14 * t_ref
+        s.close()
+
+
+THETA_CASES = [
+    # (nx, ny, limiters, order, bc_x, bc_y, sponge, evolve_steps, u0 kind)
+    (61, 37, 1 | 8, 2, 0, 0, 0, 6, "riemann"),
+    (130, 70, 2 | 8, 2, 1, 1, 0, 8, "riemann"),
+    (100, 45, 4 | 8, 2, 0, 1, 0, 8, "riemann"),
+    (64, 64, 1 | 2 | 8, 2, 1, 1, 0, 10, "riemann"),
+    (70, 33, 0, 2, 0, 0, 0, 3, "smooth"),
+    (50, 50, 1 | 8, 1, 1, 0, 0, 4, "riemann"),
+    (4, 100, 2 | 8, 2, 0, 1, 5, 30, "sod"),
+    (3, 17, 1 | 2 | 8, 2, 0, 0, 0, 5, "riemann"),
+    (300, 130, 2 | 8, 2, 1, 1, 3, 6, "riemann"),
+    (257, 65, 4 | 8, 2, 0, 0, 0, 6, "laxliu"),
+]
+
+
+def _u0(kind, nx, ny, seed=3):
+    if kind == "sod":
+        return cases.sod_y(ny, ncols=nx)
+    if kind == "laxliu":
+        u = cases.lax_liu3(max(nx, ny))
+        return np.ascontiguousarray(u[:, :ny, :nx])
+    if kind == "smooth":
+        u = cases.gaussian_bump(max(nx, ny), seed=seed, amp=0.3, sigma=0.1)
+        u = np.ascontiguousarray(u[:, :ny, :nx])
+        u[1] = 0.2 * u[0]
+        u[3] += 0.5 * u[1] ** 2 / u[0]
+        return u
+    u = cases.riemann4(max(nx, ny), seed=seed)
+    return np.ascontiguousarray(u[:, :ny, :nx])
+
+
+@pytest.mark.parametrize("case", THETA_CASES, ids=lambda c: "x".join(map(str, c[:2])) + "-l%d-o%d-bc%d%d-s%d" % c[2:7])
+def test_theta_and_state_bitwise(case, gpu):
+    """Face factors of one step and the new state equal the oracle's bit for
+    bit, over limiter sets, both boundary conditions, a sponge, sizes that
+    leave ragged strips and tiny grids."""
+    nx, ny, lims, order, bcx, bcy, sponge, ev, kind = case
+    print("theta case", case, flush=True)
+    u0 = _u0(kind, nx, ny)
+    ocfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / max(nx, ny), limiters=lims, order=order,
+                         bc_x=bcx, bc_y=bcy, sponge=sponge)
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, ev)
+    S1, tx, ty, info = oracle.step(ocfg, S)
+    s = Solver(u0, **okw(ocfg))
+    s.set_state(gpu.from_numpy(S).cuda())
+    gtx, gty = s.step_theta()
+    G = s.get_state().cpu().numpy()
+    d = s.diagnostics()
+    assert np.array_equal(gtx.cpu().numpy(), tx)
+    assert np.array_equal(gty.cpu().numpy(), ty)
+    assert np.array_equal(G, S1), "max rel err %.3e" % rel_err(G, S1)
+    assert d["n_limited"] == info.n_limited
+    assert d["n_guard"] == info.n_guard
+    s.close()
+
+
+def test_table1_on_gpu():
+    """Section 4.1 at dx = 1/20 (PP and LMP, fixed a = 10.7, 214 steps): the
+    GPU reproduces the oracle bit for bit and hence Table 1's digits."""
+    n = 20
+    u0 = cases.entropy_wave(n)
+    for lims, ref in ((1 | 8, (3.23472e-3, 3.57255e-3, 4.57474e-3)),
+                      (2 | 8, (6.90503e-3, 7.74117e-3, 1.21124e-2))):
+        ocfg = oracle.Config(nx=n, ny=n, limiters=lims, a_mode=1, a_fixed=10.7)
+        S, _ = oracle.init(ocfg, u0)
+        S, _, _, _ = oracle.run(ocfg, S, 214)
+        s = Solver(u0, **okw(ocfg))
+        s.step(214)
+        G = s.get_state().cpu().numpy()
+        assert np.array_equal(G, S)
+        e = G[0] - u0[0]
+        l1 = np.abs(e).sum() / np.abs(u0[0]).sum()
+        l2 = math.sqrt((e * e).sum() / (u0[0] ** 2).sum())
+        li = np.abs(e).max() / np.abs(u0[0]).max()
+        for v, r in zip((l1, l2, li), ref):
+            assert float("%.5e" % v) == r
+        s.close()
+
+
+def test_c1_full_size():
+    """2048^2 near-vacuum double rarefaction, PP + LMP + pressure, a = 4
+    lambda^n, outflow, in the benchmark's launch shape: the first steps equal
+    the oracle bit for bit at full size, and 1000 steps stay admissible."""
+    n = 2048
+    u0 = cases.double_rarefaction(n, seed=0)
+    ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, bc_x=1, bc_y=1)
+    s = Solver(u0, **okw(ocfg))
+    s.step(2)
+    G = s.get_state().cpu().numpy()
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, 2)
+    assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
+    del G, S
+    s.step(998)
+    m = s.moments().cpu().numpy()  # raises on a positivity event
+    d = s.diagnostics()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0
+    p = 0.4 * (m[3] - 0.5 * (m[1] ** 2 + m[2] ** 2) / m[0])
+    assert m[0].min() > 0 and p.min() > 0
+    s.close()
+
+
+def test_fp32_form_against_oracle():
+    """Blast (p = 1e3 | 1e-2, periodic, PP + pressure, a = 4 lambda^n) at
+    256^2 for 500 steps: the FP32-state form is within 1e-4 relative L1 of the
+    FP64 oracle in density and stays admissible; the FP64 form is bitwise."""
+    n, steps = 256, 500
+    u0 = cases.blast(n, seed=0)
+    ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8)
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, steps)
+    s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
+    s32.step(steps)
+    m32 = s32.moments().cpu().numpy()
+    err = np.abs(m32[0] - S[0]).sum() / np.abs(S[0]).sum()
+    print("fp32 rel L1 rho %.3e" % err)
+    assert err <= 1e-4
+    s64 = Solver(u0, **okw(ocfg))
+    s64.step(steps)
+    assert np.array_equal(s64.get_state().cpu().numpy(), S)
+    s32.close()
+    s64.close()
+
+
+def test_graph_replay_equals_eager(gpu):
+    """lbm_step_graph replays (with eager work and syncs between them) give the
+    same states as eager launches, for every slot phase."""
+    n = 96
+    u0 = cases.riemann4(n, seed=5)
+    kw = dict(limiters=1 | 2 | 8, bc_x=1, bc_y=1)
+    a = Solver(u0, **kw)
+    b = Solver(u0, **kw)
+    for rep in range(4):
+        a.step_graph(5)
+        b.step(5)
+        gpu.cuda.synchronize()
+        x = gpu.ones(1000, device="cuda").sum().item()
+        assert x == 1000
+        assert gpu.equal(a.get_state(), b.get_state()), rep
+    a.step_graph(7)
+    b.step(7)
+    assert gpu.equal(a.get_state(), b.get_state())
+    assert a.diagnostics()["t"] == b.diagnostics()["t"]
+    a.close()
+    b.close()
+
+
+def test_determinism():
+    n = 128
+    u0 = cases.riemann4(n, seed=8)
+    kw = dict(limiters=2 | 8, bc_x=1, bc_y=1)
+    a = Solver(u0, **kw)
+    b = Solver(u0, **kw)
+    b.set_launch(strip_rows=16, waves_per_group=1)
+    a.step(40)
+    b.step(40)
+    assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+    a.close()
+    b.close()
+
+
+def test_error_statuses(gpu):
+    n = 32
+    u0 = cases.riemann4(n, seed=1)
+    bad_p = B.make_params(n, n, alpha=0.4)
+    assert B.lbm_workspace_bytes(bad_p) == 0
+    ws = gpu.empty(B.lbm_workspace_bytes(B.make_params(n, n)), dtype=gpu.uint8, device="cuda")
+    u0t = gpu.from_numpy(u0).cuda()
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_init(bad_p, u0t, ws)
+    assert e.value.status == B.LBM_EINVAL
+    with pytest.raises(ValueError):
+        Solver(u0, alpha=0.4)
+    bad = u0.copy()
+    bad[0, 3, 5] = -1.0
+    with pytest.raises(B.LbmError) as e:
+        Solver(bad)
+    assert e.value.status == B.LBM_EPOSITIVITY
+    # the unlimited second-order scheme leaves the admissible set on Lax-Liu 3
+    s = Solver(cases.lax_liu3(64), limiters=0, bc_x=1, bc_y=1)
+    s.step(5)
+    _, st = s.moments(check=False)
+    assert st == B.LBM_EPOSITIVITY
+    s.close()
+    # a fixed kinetic speed below the Bouchut bound is flagged
+    s = Solver(u0, a_mode=B.LBM_A_FIXED, a_fixed=0.5)
+    s.step(1)
+    assert s.diagnostics()["bouchut"] == 1
+    _, st = s.moments(check=False)
+    assert st in (B.LBM_EBOUCHUT, B.LBM_EPOSITIVITY, B.LBM_EGUARD)
+    s.close()
