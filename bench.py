@@ -50,7 +50,23 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--calib-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
+
+
+def calibration_copy(gib):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give the
+    scale between those counters and bytes moved."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
 def time_form(form, u0t, n, steps, warmup, autotune):
@@ -178,6 +194,8 @@ def main():
     }
     if "fp32" in forms and "fp64" in forms:
         out["fp32_speedup_over_fp64"] = forms["fp32"]["value"] / forms["fp64"]["value"]
+    if a.calib_gib > 0:
+        out["calibration_copy"] = calibration_copy(a.calib_gib)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.cpu_steps)
     print(json.dumps(out))

@@ -127,6 +127,7 @@ struct lbm_ctx {
   Inst* insts_dev = nullptr;
   int* items_dev = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
   long long step = 0;
   int strip_rows = 64;
   int waves = 4;
@@ -375,14 +376,22 @@ lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
   const auto key = std::make_tuple((int)nsteps, (int)(c->step % 3), (int)(c->step & 1));
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    // record on a private stream (the legacy default stream cannot be
+    // captured); the graph is then launched on the context's stream
+    hipError_t e = hipSuccess;
+    if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
     const long long step0 = c->step;
+    hipStream_t own = c->stream;
+    c->stream = c->cap_stream;
     lbm_status st = LBM_OK;
     for (int32_t k = 0; k < nsteps && st == LBM_OK; ++k) st = launch_one(c);
+    c->stream = own;
     c->step = step0;
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(c->stream, &g);
+    e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
     hipGraphExec_t x = nullptr;
@@ -640,6 +649,7 @@ const char* lbm_last_error(const lbm_ctx* c) {
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

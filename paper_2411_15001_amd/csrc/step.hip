@@ -44,11 +44,31 @@ __device__ __forceinline__ X vmin(X a, X b) { return (b < a) ? b : a; }
 template <class X>
 __device__ __forceinline__ X vmax(X a, X b) { return (b > a) ? b : a; }
 
-// value held by lane - 1 / lane + 1 (own value at the wave ends)
-template <class X>
-__device__ __forceinline__ X from_left(X v) { return __shfl_up(v, 1u, 64); }
-template <class X>
-__device__ __forceinline__ X from_right(X v) { return __shfl_down(v, 1u, 64); }
+// Value held by lane - 1 / lane + 1 (own value at the wave ends): DPP
+// whole-wave shifts (wave_shr:1 = 0x138, wave_shl:1 = 0x130), one VALU move
+// per dword and no LDS traffic.
+__device__ __forceinline__ int dpp_left(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_right(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(dpp_left(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(dpp_right(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_left((int)(b & 0xffffffffll)), hi = dpp_left((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_right((int)(b & 0xffffffffll)), hi = dpp_right((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 __device__ __forceinline__ int map_index(int i, int n, int bc) {
   if (bc == 0) {
@@ -190,6 +210,180 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
   k.alpha = (C)s.alpha;
   k.gm1 = (C)(s.gamma - 1.0);
   return k;
+}
+
+// Strip march for limiter sets without density bounds (PP, pressure,
+// unlimited, first order): theta of the x-face i+1/2 and of the y-face L-1/2
+// is available as soon as row L arrives, so iteration L completes row L - 1.
+// Halo R = 1: lanes 1..62 produce output.
+template <class T, class C>
+__device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
+                                            int ys, int lane) {
+  constexpr int R = 1;
+  constexpr int OW = 64 - 2 * R;
+  const Scheme& sc = A.sc;
+  const int nx = in.nx, ny = in.ny;
+  const int x0 = xs * OW - R;
+  const int gi = x0 + lane;
+  const int ci = map_index(gi, nx, sc.bc_x);
+  const bool lane_out = lane >= R && lane < 64 - R && gi < nx;
+  const bool right_out = lane + 1 >= R && lane + 1 < 64 - R && gi + 1 < nx && gi + 1 >= 0;
+  const int y0 = ys * A.strip_h;
+  const int y1 = min(y0 + A.strip_h, ny);
+  const bool sponge = sc.sponge > 0;
+
+  const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+  const StepConst<T, C> K = step_const<T, C>(sc, lam);
+
+  if (xs == 0 && ys == 0 && lane == 0) {
+    sl->lam[(A.slot + 2) % 3] = 0ull;
+    sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
+  }
+
+  const T* __restrict__ src = (const T*)A.src + in.off + ci;
+  T* __restrict__ dst = (T*)A.dst + in.off + gi;
+  const long long P = A.plane;
+
+  // carried from row L - 1
+  C pu[4] = {}, pg[4] = {}, pM3[4] = {}, pd3[4] = {}, pP[4] = {};
+
+  double lmax = 0.0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0;
+
+  T raw[20];
+  {
+    const int cj = map_index(y0 - 1, ny, sc.bc_y);
+    const T* s = src + (long long)cj * nx;
+#pragma unroll
+    for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+  }
+
+  for (int L = y0 - 1; L <= y1; ++L) {
+    C u[4], uk[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (C)raw[c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) uk[k][c] = (C)raw[4 + 4 * k + c];
+    if (L < y1) {  // prefetch row L + 1
+      const int cj = map_index(L + 1, ny, sc.bc_y);
+      const T* s = src + (long long)cj * nx;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    }
+
+    C f[4], g[4];
+    fluxes(u, K.gm1, f, g);
+    C M[4][4], d[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        M[k][c] = maxw(k, u[c], f[c], g[c], K.w, K.r2a);
+        d[k][c] = M[k][c] - uk[k][c];
+      }
+    // x-face i+1/2 (right neighbour's M_2, d_2 rebuilt from its u, f, u_2)
+    C usx[4], dF[4], M2E[4], d2E[4], usy[4], dG[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C uE = from_right(u[c]);
+      const C fE = from_right(f[c]);
+      const C u2E = from_right(uk[1][c]);
+      M2E[c] = maxw(1, uE, fE, fE, K.w, K.r2a);
+      d2E[c] = M2E[c] - u2E;
+      usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
+      dF[c] = K.ac * (d[0][c] - d2E[c]);
+      // y-face L-1/2 between row L - 1 (below) and row L
+      usy[c] = C(0.5) * (pu[c] + u[c]) - (g[c] - pg[c]) * K.r2k;
+      dG[c] = K.ac * (pd3[c] - d[3][c]);
+    }
+    int gx, gy;
+    const C zero = C(0);
+    double thx = face_theta(sc, usx, dF, K.klim, zero, zero, zero, zero, gx);
+    double thy = face_theta(sc, usy, dG, K.klim, zero, zero, zero, zero, gy);
+    if (sponge) {
+      if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
+      if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
+    }
+    const bool row0 = L >= y0 && L < y1;          // row L is produced by this strip
+    const bool row1 = L - 1 >= y0 && L - 1 < y1;  // row L - 1 is completed now
+    if (row0 && right_out) {
+      n_guard += gx;
+      n_lim += (thx < 1.0);
+    }
+    if (row0 && lane_out) {
+      n_guard += gy;
+      n_lim += (thy < 1.0);
+    }
+    if (A.theta_x) {
+      const int fi = gi + 1;
+      if (row0 && (lane_out || right_out) && fi >= 0 && fi <= nx)
+        A.theta_x[(long long)L * (nx + 1) + fi] = thx;
+      if (lane_out && (row0 || row1) && L >= 0 && L <= ny)
+        A.theta_y[(long long)L * nx + gi] = thy;
+    }
+
+    const C tR = (C)thx;
+    const C tL = from_left(tR);
+    const C tB = (C)thy;
+    C fin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C u1n = from_left(M[0][c] + tR * d[0][c]);  // M_1(u_W) + theta_W d_1(W)
+      const C u2n = M2E[c] + tR * d2E[c];
+      const C u3n = pM3[c] + tB * pd3[c];
+      C s = K.alpha * u[c];
+      s = s + (u1n - tL * d[1][c]);
+      s = s + (u2n - tR * d[0][c]);
+      s = s + (u3n - tB * d[3][c]);
+      // row L - 1 completes with its face j+1/2 (= L - 1/2)
+      const C u4n = M[3][c] + tB * d[3][c];
+      fin[c] = pP[c] + (u4n - tB * pd3[c]);
+      if (row0 && lane_out) {
+        const long long o = (long long)L * nx;
+        dst[o + (4 + c) * P] = (T)u1n;
+        dst[o + (8 + c) * P] = (T)u2n;
+        dst[o + (12 + c) * P] = (T)u3n;
+      }
+      if (row1 && lane_out) {
+        const long long o = (long long)(L - 1) * nx;
+        dst[o + c * P] = (T)fin[c];
+        dst[o + (16 + c) * P] = (T)u4n;
+      }
+      pP[c] = s;
+    }
+    if (row1 && lane_out) {
+      const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
+                                      (double)(T)fin[3], sc.gamma);
+      if (l < 0.0)
+        n_bad += 1;
+      else
+        lmax = vmax(lmax, l);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      pu[c] = u[c];
+      pg[c] = g[c];
+      pM3[c] = M[2][c];
+      pd3[c] = d[2][c];
+    }
+  }
+
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_bad += __shfl_xor(n_bad, off, 64);
+    n_guard += __shfl_xor(n_guard, off, 64);
+    n_lim += __shfl_xor(n_lim, off, 64);
+  }
+  if (lane == 0) {
+    atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
+    if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
+    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
+    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+  }
 }
 
 // One strip: columns x0 .. x0 + 63, output rows [y0, y1).
@@ -403,8 +597,9 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
   }
 }
 
-template <class T, class C, bool LMP>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
+template <class T, class C, bool LMP, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int grp = blockIdx.x;
@@ -428,7 +623,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
     const long long local = item - in.item0;
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
-    march<T, C, LMP>(A, in, A.slots + ii, xs, ys, lane);
+    if (LMP)
+      march<T, C, true>(A, in, A.slots + ii, xs, ys, lane);
+    else
+      march_short<T, C>(A, in, A.slots + ii, xs, ys, lane);
   }
 }
 
@@ -507,6 +705,19 @@ __global__ void fill_f64_kernel(double* p, double v, long long n) {
     p[i] = v;
 }
 
+#ifndef VLBM_WPE_F64
+#define VLBM_WPE_F64 2
+#endif
+#ifndef VLBM_WPE_F64_LMP
+#define VLBM_WPE_F64_LMP 1
+#endif
+#ifndef VLBM_WPE_F32
+#define VLBM_WPE_F32 3
+#endif
+#ifndef VLBM_WPE_F32_LMP
+#define VLBM_WPE_F32_LMP 2
+#endif
+
 int grid_for(long long n) {
   long long g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -522,14 +733,14 @@ hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
   const dim3 grid(a.groups);
   if (precision == 0) {
     if (lmp)
-      hipLaunchKernelGGL((step_kernel<double, double, true>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((step_kernel<double, double, true, VLBM_WPE_F64_LMP>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((step_kernel<double, double, false>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((step_kernel<double, double, false, VLBM_WPE_F64>), grid, block, 0, s, a);
   } else {
     if (lmp)
-      hipLaunchKernelGGL((step_kernel<float, float, true>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((step_kernel<float, float, true, VLBM_WPE_F32_LMP>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((step_kernel<float, float, false>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((step_kernel<float, float, false, VLBM_WPE_F32>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
