@@ -69,6 +69,33 @@ __device__ __forceinline__ double from_right(double v) {
   const int lo = dpp_right((int)(b & 0xffffffffll)), hi = dpp_right((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// As above, but the lane without a source (63 for from_right_or, 0 for
+// from_left_or) receives `edge` instead of its own value: the DPP move leaves
+// that lane's destination untouched, and the destination starts as `edge`.
+__device__ __forceinline__ int dpp_right_or(int v, int e) {
+  return __builtin_amdgcn_update_dpp(e, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_left_or(int v, int e) {
+  return __builtin_amdgcn_update_dpp(e, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_right_or(float v, float e) {
+  return __int_as_float(dpp_right_or(__float_as_int(v), __float_as_int(e)));
+}
+__device__ __forceinline__ float from_left_or(float v, float e) {
+  return __int_as_float(dpp_left_or(__float_as_int(v), __float_as_int(e)));
+}
+__device__ __forceinline__ double from_right_or(double v, double e) {
+  const long long b = __double_as_longlong(v), x = __double_as_longlong(e);
+  const int lo = dpp_right_or((int)(b & 0xffffffffll), (int)(x & 0xffffffffll));
+  const int hi = dpp_right_or((int)(b >> 32), (int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_left_or(double v, double e) {
+  const long long b = __double_as_longlong(v), x = __double_as_longlong(e);
+  const int lo = dpp_left_or((int)(b & 0xffffffffll), (int)(x & 0xffffffffll));
+  const int hi = dpp_left_or((int)(b >> 32), (int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 __device__ __forceinline__ int map_index(int i, int n, int bc) {
   if (bc == 0) {
@@ -213,24 +240,29 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
 }
 
 // Strip march for limiter sets without density bounds (PP, pressure,
-// unlimited, first order): theta of the x-face i+1/2 and of the y-face L-1/2
-// is available as soon as row L arrives, so iteration L completes row L - 1.
-// Halo R = 1: lanes 1..62 produce output.
+// unlimited, first order).  Both face factors of row L are known as soon as
+// the row arrives, so iteration L completes row L - 1.  Strips are 64 columns
+// wide and aligned (x0 = 64 xs), every lane produces output: lane 0 loads the
+// state of column x0 - 1 and lane 63 that of column x0 + 64 (the halo), and
+// the two x-faces on the strip edges take their theta from the edge table
+// that edge_kernel fills before this launch with the same face code.
 template <class T, class C>
 __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                             int ys, int lane) {
-  constexpr int R = 1;
-  constexpr int OW = 64 - 2 * R;
   const Scheme& sc = A.sc;
   const int nx = in.nx, ny = in.ny;
-  const int x0 = xs * OW - R;
+  const int x0 = xs * 64;
   const int gi = x0 + lane;
   const int ci = map_index(gi, nx, sc.bc_x);
-  const bool lane_out = lane >= R && lane < 64 - R && gi < nx;
-  const bool right_out = lane + 1 >= R && lane + 1 < 64 - R && gi + 1 < nx && gi + 1 >= 0;
+  const bool lane_out = gi < nx;
+  const bool first = lane == 0, last = lane == 63;
+  // halo column: west of lane 0 (its u and u_1), east of lane 63 (u and u_2)
+  const int hcol = first ? map_index(x0 - 1, nx, sc.bc_x) : map_index(x0 + 64, nx, sc.bc_x);
+  const int hslot = first ? 4 : 8;
   const int y0 = ys * A.strip_h;
   const int y1 = min(y0 + A.strip_h, ny);
   const bool sponge = sc.sponge > 0;
+  const double* __restrict__ edge = A.edge + in.eoff + xs + (last ? 1 : 0);
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
@@ -241,9 +273,12 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
   }
 
-  const T* __restrict__ src = (const T*)A.src + in.off + ci;
-  T* __restrict__ dst = (T*)A.dst + in.off + gi;
+  // plane q of this instance starts at base + q P; a cell is addressed by a
+  // 32-bit offset row * nx + column from that uniform base
+  const T* __restrict__ sbase = (const T*)A.src + in.off;
+  T* __restrict__ dbase = (T*)A.dst + in.off;
   const long long P = A.plane;
+  const unsigned unx = (unsigned)nx;
 
   // carried from row L - 1
   C pu[4] = {}, pg[4] = {}, pM3[4] = {}, pd3[4] = {}, pP[4] = {};
@@ -251,31 +286,57 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   double lmax = 0.0;
   unsigned n_bad = 0, n_guard = 0, n_lim = 0;
 
-  T raw[20];
+  T raw[20], hraw[8];
+  double eraw = 0.0;
   {
-    const int cj = map_index(y0 - 1, ny, sc.bc_y);
-    const T* s = src + (long long)cj * nx;
+    const unsigned ro = (unsigned)map_index(y0 - 1, ny, sc.bc_y) * unx;
+    const unsigned o = ro + (unsigned)ci;
 #pragma unroll
-    for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+    if (first || last) {
+      const unsigned oh = ro + (unsigned)hcol;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
+      if (y0 - 1 >= 0 && y0 - 1 < ny) eraw = edge[(long long)(y0 - 1) * in.nk];
+    }
   }
 
   for (int L = y0 - 1; L <= y1; ++L) {
-    C u[4], uk[4][4];
+    C u[4], uk[4][4], hu[4], hk[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = (C)raw[c];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int c = 0; c < 4; ++c) uk[k][c] = (C)raw[4 + 4 * k + c];
-    if (L < y1) {  // prefetch row L + 1
-      const int cj = map_index(L + 1, ny, sc.bc_y);
-      const T* s = src + (long long)cj * nx;
 #pragma unroll
-      for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    for (int c = 0; c < 4; ++c) {
+      hu[c] = (C)hraw[c];
+      hk[c] = (C)hraw[4 + c];
+    }
+    const double th_edge = eraw;
+    if (L < y1) {  // prefetch row L + 1
+      const unsigned ro = (unsigned)map_index(L + 1, ny, sc.bc_y) * unx;
+      const unsigned o = ro + (unsigned)ci;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+      if (first || last) {
+        const unsigned oh = ro + (unsigned)hcol;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
+        // the table has rows 0 .. ny - 1; ghost rows only feed rows that
+        // this strip does not store
+        eraw = (L + 1 >= 0 && L + 1 < ny) ? edge[(long long)(L + 1) * in.nk] : 0.0;
+      }
     }
 
-    C f[4], g[4];
+    C f[4], g[4], hf[4], hg[4];
     fluxes(u, K.gm1, f, g);
+    fluxes(hu, K.gm1, hf, hg);
     C M[4][4], d[4][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -284,13 +345,14 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
         M[k][c] = maxw(k, u[c], f[c], g[c], K.w, K.r2a);
         d[k][c] = M[k][c] - uk[k][c];
       }
-    // x-face i+1/2 (right neighbour's M_2, d_2 rebuilt from its u, f, u_2)
+    // x-face i+1/2: the east neighbour's M_2, d_2 from its u, f and u_2
     C usx[4], dF[4], M2E[4], d2E[4], usy[4], dG[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const C uE = from_right(u[c]);
-      const C fE = from_right(f[c]);
-      const C u2E = from_right(uk[1][c]);
+      // lanes 0..62 take lane + 1; lane 63 takes its halo (the east column)
+      const C uE = from_right_or(u[c], hu[c]);
+      const C fE = from_right_or(f[c], hf[c]);
+      const C u2E = from_right_or(uk[1][c], hk[c]);
       M2E[c] = maxw(1, uE, fE, fE, K.w, K.r2a);
       d2E[c] = M2E[c] - u2E;
       usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
@@ -307,9 +369,12 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
     }
+    if (last) thx = th_edge;  // east edge face of the strip
     const bool row0 = L >= y0 && L < y1;          // row L is produced by this strip
     const bool row1 = L - 1 >= y0 && L - 1 < y1;  // row L - 1 is completed now
-    if (row0 && right_out) {
+    // faces counted here: the x-face i+1/2 of lanes 0..62 (the edge faces
+    // are counted by edge_kernel) and the y-face L-1/2 of every lane
+    if (row0 && !last && gi + 1 < nx) {
       n_guard += gx;
       n_lim += (thx < 1.0);
     }
@@ -318,20 +383,21 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       n_lim += (thy < 1.0);
     }
     if (A.theta_x) {
-      const int fi = gi + 1;
-      if (row0 && (lane_out || right_out) && fi >= 0 && fi <= nx)
-        A.theta_x[(long long)L * (nx + 1) + fi] = thx;
-      if (lane_out && (row0 || row1) && L >= 0 && L <= ny)
-        A.theta_y[(long long)L * nx + gi] = thy;
+      if (row0 && !last && gi + 1 <= nx) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
+      if (lane_out && (row0 || row1) && L >= 0 && L <= ny) A.theta_y[(long long)L * nx + gi] = thy;
     }
 
     const C tR = (C)thx;
-    const C tL = from_left(tR);
+    const C tL = from_left_or(tR, (C)th_edge);  // lane 0: the west edge face
     const C tB = (C)thy;
     C fin[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const C u1n = from_left(M[0][c] + tR * d[0][c]);  // M_1(u_W) + theta_W d_1(W)
+      // M_1(u_W) + theta_W d_1(W): from lane - 1, or from the halo for lane 0
+      const C o1n = M[0][c] + tR * d[0][c];
+      const C hM1 = maxw(0, hu[c], hf[c], hg[c], K.w, K.r2a);
+      const C hd1 = hM1 - hk[c];
+      const C u1n = from_left_or(o1n, hM1 + tL * hd1);
       const C u2n = M2E[c] + tR * d2E[c];
       const C u3n = pM3[c] + tB * pd3[c];
       C s = K.alpha * u[c];
@@ -342,15 +408,15 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       const C u4n = M[3][c] + tB * d[3][c];
       fin[c] = pP[c] + (u4n - tB * pd3[c]);
       if (row0 && lane_out) {
-        const long long o = (long long)L * nx;
-        dst[o + (4 + c) * P] = (T)u1n;
-        dst[o + (8 + c) * P] = (T)u2n;
-        dst[o + (12 + c) * P] = (T)u3n;
+        const unsigned o = (unsigned)L * unx + (unsigned)gi;
+        (dbase + (4 + c) * P)[o] = (T)u1n;
+        (dbase + (8 + c) * P)[o] = (T)u2n;
+        (dbase + (12 + c) * P)[o] = (T)u3n;
       }
       if (row1 && lane_out) {
-        const long long o = (long long)(L - 1) * nx;
-        dst[o + c * P] = (T)fin[c];
-        dst[o + (16 + c) * P] = (T)u4n;
+        const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
+        (dbase + c * P)[o] = (T)fin[c];
+        (dbase + (16 + c) * P)[o] = (T)u4n;
       }
       pP[c] = s;
     }
@@ -381,6 +447,88 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   if (lane == 0) {
     atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
     if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
+    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
+    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+  }
+}
+
+// theta of the x-faces on the edges of the full-width strips, x = 64 k - 1/2,
+// k = 0 .. nk - 1, for every row (limiter sets without density bounds).  The
+// expressions are those of march_short for the face of a lane and its east
+// neighbour, so the table holds the values that lane would compute.
+template <class T, class C>
+__global__ __launch_bounds__(256) void edge_kernel(StepArgs A) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = f < A.n_edge;
+  int ii = 0;
+  Inst in = A.inst0;
+  if (active && A.n_inst > 1) {
+    int lo = 0, hi = A.n_inst - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.insts[mid].eoff <= f) lo = mid; else hi = mid - 1;
+    }
+    ii = lo;
+    in = A.insts[ii];
+  }
+  unsigned n_guard = 0, n_lim = 0;
+  Slots* sl = A.slots + ii;
+  if (active) {
+    const Scheme& sc = A.sc;
+    const long long local = f - in.eoff;
+    const int j = (int)(local / in.nk), k = (int)(local % in.nk);
+    const int nx = in.nx, ny = in.ny;
+    const int a = 64 * k - 1, b = 64 * k;  // the face lies between columns a and b
+    const int ca = map_index(a, nx, sc.bc_x), cb = map_index(b, nx, sc.bc_x);
+    const int cj = map_index(j, ny, sc.bc_y);
+    const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+    const StepConst<T, C> K = step_const<T, C>(sc, lam);
+    const T* base = (const T*)A.src + in.off + (long long)cj * nx;
+    const long long P = A.plane;
+    C uL[4], uR[4], u1L[4], u2R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      uL[c] = (C)base[c * P + ca];
+      uR[c] = (C)base[c * P + cb];
+      u1L[c] = (C)base[(4 + c) * P + ca];
+      u2R[c] = (C)base[(8 + c) * P + cb];
+    }
+    C fL[4], gL[4], fR[4], gR[4];
+    fluxes(uL, K.gm1, fL, gL);
+    fluxes(uR, K.gm1, fR, gR);
+    C usx[4], dF[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C d1 = maxw(0, uL[c], fL[c], gL[c], K.w, K.r2a) - u1L[c];
+      const C M2E = maxw(1, uR[c], fR[c], fR[c], K.w, K.r2a);
+      const C d2E = M2E - u2R[c];
+      usx[c] = C(0.5) * (uL[c] + uR[c]) - (fR[c] - fL[c]) * K.r2k;
+      dF[c] = K.ac * (d1 - d2E);
+    }
+    int guard;
+    const C zero = C(0);
+    double th = face_theta(sc, usx, dF, K.klim, zero, zero, zero, zero, guard);
+    if (sc.sponge > 0 && (in_sponge(sc, a, j, nx, ny) || in_sponge(sc, b, j, nx, ny))) th = 0.0;
+    A.edge[f] = th;
+    if (b >= 0 && b < nx) {
+      n_guard = (unsigned)guard;
+      n_lim = th < 1.0 ? 1u : 0u;
+    }
+    if (A.theta_x && b <= nx) A.theta_x[(long long)j * (nx + 1) + b] = th;
+  }
+  // one atomic per wave and instance (waves may straddle two instances)
+  const unsigned long long same = __ballot(ii == __shfl(ii, 0, 64));
+  if (same == ~0ull) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      n_guard += __shfl_xor(n_guard, off, 64);
+      n_lim += __shfl_xor(n_lim, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
+      if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+    }
+  } else {
     if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
     if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
   }
@@ -601,7 +749,8 @@ template <class T, class C, bool LMP, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // uniform across the wave: lets the compiler keep work-item data in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int grp = blockIdx.x;
   if (A.xcd_remap && (A.groups & 7) == 0) {
     // groups are dispatched round-robin over the 8 XCDs: give each XCD one
@@ -706,13 +855,13 @@ __global__ void fill_f64_kernel(double* p, double v, long long n) {
 }
 
 #ifndef VLBM_WPE_F64
-#define VLBM_WPE_F64 2
+#define VLBM_WPE_F64 1
 #endif
 #ifndef VLBM_WPE_F64_LMP
 #define VLBM_WPE_F64_LMP 1
 #endif
 #ifndef VLBM_WPE_F32
-#define VLBM_WPE_F32 3
+#define VLBM_WPE_F32 2
 #endif
 #ifndef VLBM_WPE_F32_LMP
 #define VLBM_WPE_F32_LMP 2
@@ -731,6 +880,13 @@ hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
   const dim3 block(64 * a.waves_per_group);
   const dim3 grid(a.groups);
+  if (!lmp && a.n_edge > 0) {
+    const dim3 eg((unsigned)((a.n_edge + 255) / 256));
+    if (precision == 0)
+      hipLaunchKernelGGL((edge_kernel<double, double>), eg, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((edge_kernel<float, float>), eg, dim3(256), 0, s, a);
+  }
   if (precision == 0) {
     if (lmp)
       hipLaunchKernelGGL((step_kernel<double, double, true, VLBM_WPE_F64_LMP>), grid, block, 0, s, a);
