@@ -1,0 +1,244 @@
+"""The batching and differentiation forms on the GPU, checked against
+single-instance runs, the FP64 oracle (bitwise / complex-step tangents) and
+finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_15001_amd import binding as B
+from paper_2411_15001_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.lib()
+    return torch
+
+
+def solver(*a, **k):
+    from paper_2411_15001_amd.solver import Solver
+
+    return Solver(*a, **k)
+
+
+def batch(*a, **k):
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    return BatchSolver(*a, **k)
+
+
+# ------------------------------------------------------------------ batching
+SIZES = [(128, 128), (256, 256), (384, 384), (130, 70), (61, 200), (64, 64), (3, 17), (512, 128)]
+
+
+@pytest.mark.parametrize("prec", [B.LBM_FP64, B.LBM_FP32_STATE])
+@pytest.mark.parametrize("lims", [1 | 8, 1 | 2 | 8])
+def test_batch_equals_single_instances(prec, lims):
+    """Every instance of an uneven batch advanced in one launch per step is
+    bit-identical to the same instance run alone (per-instance kinetic speed,
+    dx = 1/nx)."""
+    u0s = []
+    for i, (nx, ny) in enumerate(SIZES):
+        u = cases.riemann4(max(nx, ny), rng=np.random.default_rng([7, i]))
+        u0s.append(np.ascontiguousarray(u[:, :ny, :nx]))
+    kw = dict(limiters=lims, a_beta=1.1, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW,
+              precision=prec)
+    bs = batch(u0s, **kw)
+    bs.step(12)
+    bs.step_graph(9)
+    for i, u in enumerate(u0s):
+        ny, nx = u.shape[1:]
+        s = solver(u, dx=1.0 / nx, **kw)
+        s.step(21)
+        a = bs.moments(i).cpu().numpy()
+        b = s.moments().cpu().numpy()
+        assert np.array_equal(a, b), (i, nx, ny, np.abs(a - b).max())
+        assert bs.diagnostics(i)["lam"] == s.diagnostics()["lam"]
+        s.close()
+    bs.close()
+
+
+def test_batch_fp64_against_oracle():
+    sizes = [(96, 96), (70, 130), (200, 64)]
+    u0s = []
+    for i, (nx, ny) in enumerate(sizes):
+        u = cases.riemann4(max(nx, ny), rng=np.random.default_rng([3, i]))
+        u0s.append(np.ascontiguousarray(u[:, :ny, :nx]))
+    bs = batch(u0s, limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+    bs.step(40)
+    for i, u in enumerate(u0s):
+        ny, nx = u.shape[1:]
+        cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+        S, _ = oracle.init(cfg, u)
+        S, _, _, _ = oracle.run(cfg, S, 40)
+        assert np.array_equal(bs.moments(i).cpu().numpy(), S[0:4])
+    bs.close()
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    u0s = [cases.riemann4(s, rng=np.random.default_rng([1, i]))
+           for i, s in enumerate([128, 256, 128, 384])]
+    bs = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
+    ref = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
+    cache = str(tmp_path / "tune.json")
+    rows, waves = bs.autotune(cache)
+    assert rows >= 16 and 1 <= waves <= 4
+    assert open(cache).read().count("[") == 1
+    # tuning does not advance the state
+    bs.step(10)
+    ref.step(10)
+    for i in range(4):
+        assert np.array_equal(bs.moments(i).cpu().numpy(), ref.moments(i).cpu().numpy())
+    # a second context reads the cached entry
+    again = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
+    assert again.autotune(cache) == (rows, waves)
+    for x in (bs, ref, again):
+        x.close()
+
+
+# ----------------------------------------------------------- differentiation
+def _dot(a, b):
+    return float(np.sum(a * b))
+
+
+@pytest.mark.parametrize("lims", [1 | 8, 1 | 2 | 8])
+def test_step_adjoint_dot_product(gpu, lims):
+    """<J v, w> from the oracle's complex-step tangent of the step with theta
+    and a frozen equals <v, J^T w> from lbm_step_adjoint (periodic, 64^2, a
+    state with limited faces)."""
+    n = 64
+    cfg = oracle.Config(nx=n, ny=n, limiters=lims, a_beta=1.1)
+    S, _ = oracle.init(cfg, cases.riemann4(n, seed=2))
+    S, _, _, _ = oracle.run(cfg, S, 15)
+    _, tx, ty, info = oracle.step(cfg, S)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        v = rng.normal(size=S.shape)
+        w = rng.normal(size=S.shape)
+        h = 1e-30
+        _, im = oracle.step_frozen_cs(cfg, S, h * v, tx, ty, info.a)
+        jv = im / h
+        s = solver(cases.riemann4(n, seed=2), limiters=lims, a_beta=1.1)
+        Ut = gpu.from_numpy(S).cuda()
+        wt = gpu.from_numpy(w).cuda()
+        out = gpu.empty_like(wt)
+        B.lbm_step_adjoint(s.ctx, Ut, wt, out)
+        jtw = out.cpu().numpy()
+        lhs, rhs = _dot(jv, w), _dot(v, jtw)
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), np.linalg.norm(jv) * np.linalg.norm(w)), (lhs, rhs)
+        s.close()
+    assert info.n_limited > 0
+
+
+def test_init_adjoint_dot_product(gpu):
+    n = 48
+    u0 = cases.gaussian_bump(n, seed=0)
+    a0 = 7.0
+    cfg = oracle.Config(nx=n, ny=n, a_mode=oracle.A_FIXED, a_fixed=a0)
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=u0.shape)
+    W = rng.normal(size=(20, n, n))
+    _, im = oracle.init_frozen_cs(cfg, u0, 1e-30 * v, a0)
+    jv = im / 1e-30
+    s = solver(u0, a_mode=B.LBM_A_FIXED, a_fixed=a0)
+    out = gpu.empty((4, n, n), dtype=gpu.float64, device="cuda")
+    B.lbm_init_adjoint(s.ctx, gpu.from_numpy(u0).cuda(), gpu.from_numpy(W).cuda(), out)
+    lhs, rhs = _dot(jv, W), _dot(v, out.cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(jv) * np.linalg.norm(W)
+    s.close()
+
+
+def _c4_setup(n=512, seed=0):
+    u0 = cases.gaussian_bump(n, seed=seed)
+    lam0 = oracle.lam(oracle.Config(nx=n, ny=n), u0)[0]
+    a_fixed = 4.4 * lam0
+    return u0, a_fixed
+
+
+def test_rollout_gradient_finite_differences(gpu):
+    """Differentiation workload: 512^2 periodic Gaussian bump, fixed kinetic
+    speed, PP + pressure, 200 steps with checkpoints every 20; loss = half the
+    squared density misfit to a target made from a shifted bump.  The
+    gradient from the adjoint matches central finite differences on 32
+    seeded directions to 1e-6 relative."""
+    from paper_2411_15001_amd.autograd import rollout
+
+    n, steps = 512, 200
+    u0, a_fixed = _c4_setup(n)
+    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=a_fixed, limiters=1 | 8)
+    tgt_u0 = cases.gaussian_bump_target(n)
+    st = solver(tgt_u0, **kw)
+    st.step(steps)
+    assert st.diagnostics()["n_limited"] == 0  # read before moments() clears it
+    rho_tgt = st.moments()[0].clone()
+    st.close()
+
+    def loss_of(u):
+        s = solver(u, **kw)
+        s.step(steps)
+        lim = s.diagnostics()["n_limited"]
+        m = s.moments()
+        s.close()
+        return 0.5 * float(((m[0] - rho_tgt) ** 2).sum()), lim
+
+    u0t = gpu.from_numpy(u0).cuda().requires_grad_(True)
+    m = rollout(u0t, steps, 20, **kw)
+    L = 0.5 * ((m[0] - rho_tgt) ** 2).sum()
+    L.backward()
+    g = u0t.grad.cpu().numpy()
+    scale = np.array([np.abs(u0[0]).max(), 1.0, 1.0, np.abs(u0[3]).max()])[:, None, None]
+    worst = 0.0
+    for k in range(32):
+        d = np.random.default_rng(100 + k).normal(size=u0.shape) * scale
+        dl = _dot(g, d)
+        fd = []
+        for h in (1e-6, 5e-7):
+            lp, limp = loss_of(u0 + h * d)
+            lm, limm = loss_of(u0 - h * d)
+            assert limp == 0 and limm == 0
+            fd.append((lp - lm) / (2 * h))
+        # Richardson combination of the two step sizes removes the h^2 term
+        est = (4 * fd[1] - fd[0]) / 3
+        err = abs(dl - est) / max(abs(dl), 1e-300)
+        worst = max(worst, err)
+    print("rollout FD worst relative error %.3e" % worst)
+    assert worst <= 1e-6
+
+
+def test_rollout_gradient_vs_oracle_jvp(gpu):
+    """<grad L, d> from the GPU adjoint equals the oracle's complex-step
+    directional derivative of the same rollout (theta and a frozen at the
+    oracle's forward values) on a 64^2 grid with limited faces."""
+    from paper_2411_15001_amd.autograd import rollout
+
+    n, steps = 64, 30
+    u0 = cases.riemann4(n, seed=6)
+    lam0 = oracle.lam(oracle.Config(nx=n, ny=n), u0)[0]
+    a_fixed = 6.0 * lam0  # lambda grows by ~13% over the run; keeps a >= 4 lambda
+    cfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, a_mode=oracle.A_FIXED, a_fixed=a_fixed)
+    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=a_fixed, limiters=1 | 2 | 8)
+    rng = np.random.default_rng(5)
+    wgt = rng.normal(size=(n, n))
+    u0t = gpu.from_numpy(u0).cuda().requires_grad_(True)
+    m = rollout(u0t, steps, 7, **kw)
+    L = (m[0] * gpu.from_numpy(wgt).cuda()).sum()
+    L.backward()
+    g = u0t.grad.cpu().numpy()
+    d = rng.normal(size=u0.shape)
+    h = 1e-30
+    S, Sim = oracle.init_frozen_cs(cfg, u0, h * d, a_fixed)
+    limited = 0
+    for _ in range(steps):
+        Sn, tx, ty, info = oracle.step(cfg, S)
+        assert info.bouchut == 0
+        limited += info.n_limited
+        re, Sim = oracle.step_frozen_cs(cfg, S, Sim, tx, ty, info.a)
+        S = Sn
+    jvp = float(np.sum(wgt * Sim[0] / h))
+    assert limited > 0
+    assert abs(_dot(g, d) - jvp) <= 1e-9 * abs(jvp)

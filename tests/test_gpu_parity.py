@@ -172,25 +172,55 @@ def test_c1_full_size():
 
 
 def test_fp32_form_against_oracle():
-    """Blast (p = 1e3 | 1e-2, periodic, PP + pressure, a = 4 lambda^n) at
-    256^2 for 500 steps: the FP32-state form is within 1e-4 relative L1 of the
-    FP64 oracle in density and stays admissible; the FP64 form is bitwise."""
-    n, steps = 256, 500
+    """FP32-state form (float32 collide/stream, float64 theta solve and
+    wavespeed) against the FP64 oracle, relative L1 error of the density.
+
+    Blast (p = 1e3 | 1e-2, periodic, PP + pressure, a = 4 lambda^n) at 256^2:
+    <= 1e-4 after 100 steps.  After 500 steps the PP-limited blast amplifies
+    any perturbation: the oracle itself, started from data perturbed by one
+    float32 rounding (6e-8 relative), moves by ~3e-2, so the bound there is a
+    small multiple of that floor.  Smooth data (Section 4.1 wave, 64^2,
+    685 steps): <= 1e-5.  The FP64 form stays bit-identical throughout."""
+    n = 256
     u0 = cases.blast(n, seed=0)
     ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8)
-    S, _ = oracle.init(ocfg, u0)
-    S, _, _, _ = oracle.run(ocfg, S, steps)
+    S0, _ = oracle.init(ocfg, u0)
+    S100, _, _, _ = oracle.run(ocfg, S0, 100)
+    S500, _, _, _ = oracle.run(ocfg, S100, 400)
+    rng = np.random.default_rng(1)
+    Sp, _ = oracle.init(ocfg, u0 * (1 + 6e-8 * rng.uniform(-1, 1, u0.shape)))
+    Sp, _, _, _ = oracle.run(ocfg, Sp, 500)
+
+    def l1(a, b):
+        return np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum()
+
+    floor = l1(Sp, S500)
     s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
-    s32.step(steps)
-    m32 = s32.moments().cpu().numpy()
-    err = np.abs(m32[0] - S[0]).sum() / np.abs(S[0]).sum()
-    print("fp32 rel L1 rho %.3e" % err)
-    assert err <= 1e-4
+    s32.step(100)
+    e100 = l1(s32.moments().cpu().numpy(), S100)
+    s32.step(400)
+    e500 = l1(s32.moments().cpu().numpy(), S500)
+    print("fp32 blast rel L1 rho: 100 steps %.3e, 500 steps %.3e (oracle floor %.3e)"
+          % (e100, e500, floor))
+    assert e100 <= 1e-4
+    assert e500 <= 3 * floor + 1e-4
+    assert s32.diagnostics()["n_bad"] == 0
     s64 = Solver(u0, **okw(ocfg))
-    s64.step(steps)
-    assert np.array_equal(s64.get_state().cpu().numpy(), S)
+    s64.step(500)
+    assert np.array_equal(s64.get_state().cpu().numpy(), S500)
     s32.close()
     s64.close()
+    n = 64
+    u0 = cases.entropy_wave(n)
+    ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8, a_mode=1, a_fixed=10.7)
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, 685)
+    s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
+    s32.step(685)
+    e = l1(s32.moments().cpu().numpy(), S)
+    print("fp32 entropy wave rel L1 rho %.3e" % e)
+    assert e <= 1e-5
+    s32.close()
 
 
 def test_graph_replay_equals_eager(gpu):
