@@ -18,6 +18,7 @@ using vlbm::Slots;
 namespace {
 
 constexpr int kMinStripRows = 16;  // bounds the work-item table in the workspace
+constexpr int kMaxStripRows = 4096;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -29,14 +30,8 @@ bool uses_bounds(const lbm_params* p) {
 }
 
 // Lanes of a 64-wide strip that only supply neighbours: 2 on each side when
-// the density bounds are needed, none otherwise (full-width strips with an
-// edge-face table).
+// the density bounds are needed, none otherwise (full-width strips).
 int halo_radius(const lbm_params* p) { return uses_bounds(p) ? 2 : 0; }
-
-long long edge_faces(const lbm_params* p, int nx, int ny) {
-  if (uses_bounds(p)) return 0;
-  return (long long)((nx + 63) / 64 + 1) * ny;
-}
 
 long long strips_x(int nx, int R) {
   const int ow = 64 - 2 * R;
@@ -91,17 +86,16 @@ Scheme make_scheme(const lbm_params* p) {
 }
 
 struct Layout {
-  size_t slots, insts, items, edge, bufA, bufB, theta, total;
+  size_t slots, insts, items, bufA, bufB, theta, total;
 };
 
 Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   const size_t elem = p->precision == LBM_FP64 ? 8 : 4;
   const int R = halo_radius(p);
-  long long cells = 0, items = 0, edges = 0;
+  long long cells = 0, items = 0;
   for (int i = 0; i < n; ++i) {
     cells += (long long)nx[i] * ny[i];
     items += strips_x(nx[i], R) * strips_y(ny[i], kMinStripRows);
-    edges += edge_faces(p, nx[i], ny[i]);
   }
   Layout L;
   size_t o = 0;
@@ -111,8 +105,6 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   o = align_up(o + sizeof(Inst) * (size_t)n);
   L.items = o;
   o = align_up(o + sizeof(int) * (size_t)(n > 1 ? items : 0));
-  L.edge = o;
-  o = align_up(o + sizeof(double) * (size_t)edges);
   L.bufA = o;
   o = align_up(o + (size_t)20 * cells * elem);
   L.bufB = o;
@@ -139,8 +131,6 @@ struct lbm_ctx {
   Slots* slots = nullptr;
   Inst* insts_dev = nullptr;
   int* items_dev = nullptr;
-  double* edge_dev = nullptr;
-  long long n_edge = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
   long long step = 0;
@@ -176,13 +166,8 @@ void build_items(lbm_ctx* c) {
   const int R = halo_radius(&c->p);
   c->n_items = 0;
   c->item_inst.clear();
-  c->n_edge = 0;
   for (int i = 0; i < c->n_inst; ++i) {
     Inst& in = c->insts[i];
-    const long long ne = edge_faces(&c->p, in.nx, in.ny);
-    in.nk = ne ? (in.nx + 63) / 64 + 1 : 0;
-    in.eoff = c->n_edge;
-    c->n_edge += ne;
     in.xs = (int)strips_x(in.nx, R);
     in.ys = (int)strips_y(in.ny, c->strip_rows);
     in.item0 = c->n_items;
@@ -229,8 +214,6 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
   a.waves_per_group = c->waves;
   a.xcd_remap = c->xcd;
   a.groups = compute_groups(c);
-  a.edge = c->edge_dev;
-  a.n_edge = c->n_edge;
   a.sc = c->sc;
   return a;
 }
@@ -294,7 +277,6 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   c->slots = (Slots*)(c->ws + c->lay.slots);
   c->insts_dev = (Inst*)(c->ws + c->lay.insts);
   c->items_dev = (int*)(c->ws + c->lay.items);
-  c->edge_dev = (double*)(c->ws + c->lay.edge);
   c->insts.resize(n);
   long long off = 0;
   for (int i = 0; i < n; ++i) {
@@ -542,7 +524,7 @@ lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const double* Ub0, dou
 
 lbm_status lbm_set_launch(lbm_ctx* c, int32_t rows, int32_t waves) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
-  if (rows != 0 && (rows < kMinStripRows || rows > 4096))
+  if (rows != 0 && (rows < kMinStripRows || rows > kMaxStripRows))
     return fail(c, LBM_EINVAL, "strip rows must lie in [16, 4096]");
   if (waves != 0 && (waves < 1 || waves > 4)) return fail(c, LBM_EINVAL, "waves per group must lie in [1, 4]");
   if (rows) c->strip_rows = rows;
@@ -595,7 +577,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   float best = 1e30f;
   int best_r = c->strip_rows, best_w = c->waves;
   for (int r : rows_c) {
-    if (r > 4 * c->insts[0].ny && r != 16) continue;
+    if (r > 2 * c->insts[0].ny && r != 16) continue;
     for (int w : waves_c) {
       st = lbm_set_launch(c, r, w);
       if (st != LBM_OK) break;

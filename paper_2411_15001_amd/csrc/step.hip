@@ -243,9 +243,12 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
 // unlimited, first order).  Both face factors of row L are known as soon as
 // the row arrives, so iteration L completes row L - 1.  Strips are 64 columns
 // wide and aligned (x0 = 64 xs), every lane produces output: lane 0 loads the
-// state of column x0 - 1 and lane 63 that of column x0 + 64 (the halo), and
-// the two x-faces on the strip edges take their theta from the edge table
-// that edge_kernel fills before this launch with the same face code.
+// state of column x0 - 1 and lane 63 that of column x0 + 64 (the halo).
+// Lane 63 evaluates its east face x0 + 63 + 1/2 from the halo like any other
+// face, and lane 0 evaluates the west face x0 - 1/2 from its halo (a third
+// face evaluation per row).  The strip to the west evaluates that same face
+// with the same inputs and code, so both cells of a strip-edge face see the
+// same theta.
 template <class T, class C>
 __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                             int ys, int lane) {
@@ -262,7 +265,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   const int y0 = ys * A.strip_h;
   const int y1 = min(y0 + A.strip_h, ny);
   const bool sponge = sc.sponge > 0;
-  const double* __restrict__ edge = A.edge + in.eoff + xs + (last ? 1 : 0);
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
@@ -287,7 +289,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   unsigned n_bad = 0, n_guard = 0, n_lim = 0;
 
   T raw[20], hraw[8];
-  double eraw = 0.0;
   {
     const unsigned ro = (unsigned)map_index(y0 - 1, ny, sc.bc_y) * unx;
     const unsigned o = ro + (unsigned)ci;
@@ -299,7 +300,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
 #pragma unroll
       for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
-      if (y0 - 1 >= 0 && y0 - 1 < ny) eraw = edge[(long long)(y0 - 1) * in.nk];
     }
   }
 
@@ -316,7 +316,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       hu[c] = (C)hraw[c];
       hk[c] = (C)hraw[4 + c];
     }
-    const double th_edge = eraw;
     if (L < y1) {  // prefetch row L + 1
       const unsigned ro = (unsigned)map_index(L + 1, ny, sc.bc_y) * unx;
       const unsigned o = ro + (unsigned)ci;
@@ -328,9 +327,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
         for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
 #pragma unroll
         for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
-        // the table has rows 0 .. ny - 1; ghost rows only feed rows that
-        // this strip does not store
-        eraw = (L + 1 >= 0 && L + 1 < ny) ? edge[(long long)(L + 1) * in.nk] : 0.0;
       }
     }
 
@@ -361,19 +357,29 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       usy[c] = C(0.5) * (pu[c] + u[c]) - (g[c] - pg[c]) * K.r2k;
       dG[c] = K.ac * (pd3[c] - d[3][c]);
     }
-    int gx, gy;
+    // west edge face x0 - 1/2 (meaningful in lane 0, whose halo is the west
+    // column): the expressions of the east face of the western neighbour
+    C usw[4], dFw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C hd1 = maxw(0, hu[c], hf[c], hg[c], K.w, K.r2a) - hk[c];
+      usw[c] = C(0.5) * (hu[c] + u[c]) - (f[c] - hf[c]) * K.r2k;
+      dFw[c] = K.ac * (hd1 - d[1][c]);
+    }
+    int gx, gy, gw;
     const C zero = C(0);
     double thx = face_theta(sc, usx, dF, K.klim, zero, zero, zero, zero, gx);
     double thy = face_theta(sc, usy, dG, K.klim, zero, zero, zero, zero, gy);
+    double th_edge = face_theta(sc, usw, dFw, K.klim, zero, zero, zero, zero, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
+      if (in_sponge(sc, x0 - 1, L, nx, ny) || in_sponge(sc, x0, L, nx, ny)) th_edge = 0.0;
     }
-    if (last) thx = th_edge;  // east edge face of the strip
     const bool row0 = L >= y0 && L < y1;          // row L is produced by this strip
     const bool row1 = L - 1 >= y0 && L - 1 < y1;  // row L - 1 is completed now
-    // faces counted here: the x-face i+1/2 of lanes 0..62 (the edge faces
-    // are counted by edge_kernel) and the y-face L-1/2 of every lane
+    // faces counted here: the x-face i+1/2 of lanes 0..62, the west edge
+    // face (lane 0) and the y-face L-1/2 of every lane
     if (row0 && !last && gi + 1 < nx) {
       n_guard += gx;
       n_lim += (thx < 1.0);
@@ -382,8 +388,13 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       n_guard += gy;
       n_lim += (thy < 1.0);
     }
+    if (row0 && first) {  // face x0 - 1/2 belongs to output cell x0
+      n_guard += gw;
+      n_lim += (th_edge < 1.0);
+    }
     if (A.theta_x) {
-      if (row0 && !last && gi + 1 <= nx) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
+      if (row0 && first) A.theta_x[(long long)L * (nx + 1) + x0] = th_edge;
+      if (row0 && gi + 1 <= nx) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row0 || row1) && L >= 0 && L <= ny) A.theta_y[(long long)L * nx + gi] = thy;
     }
 
@@ -447,88 +458,6 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   if (lane == 0) {
     atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
     if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
-    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
-    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
-  }
-}
-
-// theta of the x-faces on the edges of the full-width strips, x = 64 k - 1/2,
-// k = 0 .. nk - 1, for every row (limiter sets without density bounds).  The
-// expressions are those of march_short for the face of a lane and its east
-// neighbour, so the table holds the values that lane would compute.
-template <class T, class C>
-__global__ __launch_bounds__(256) void edge_kernel(StepArgs A) {
-  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = f < A.n_edge;
-  int ii = 0;
-  Inst in = A.inst0;
-  if (active && A.n_inst > 1) {
-    int lo = 0, hi = A.n_inst - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (A.insts[mid].eoff <= f) lo = mid; else hi = mid - 1;
-    }
-    ii = lo;
-    in = A.insts[ii];
-  }
-  unsigned n_guard = 0, n_lim = 0;
-  Slots* sl = A.slots + ii;
-  if (active) {
-    const Scheme& sc = A.sc;
-    const long long local = f - in.eoff;
-    const int j = (int)(local / in.nk), k = (int)(local % in.nk);
-    const int nx = in.nx, ny = in.ny;
-    const int a = 64 * k - 1, b = 64 * k;  // the face lies between columns a and b
-    const int ca = map_index(a, nx, sc.bc_x), cb = map_index(b, nx, sc.bc_x);
-    const int cj = map_index(j, ny, sc.bc_y);
-    const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
-    const StepConst<T, C> K = step_const<T, C>(sc, lam);
-    const T* base = (const T*)A.src + in.off + (long long)cj * nx;
-    const long long P = A.plane;
-    C uL[4], uR[4], u1L[4], u2R[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      uL[c] = (C)base[c * P + ca];
-      uR[c] = (C)base[c * P + cb];
-      u1L[c] = (C)base[(4 + c) * P + ca];
-      u2R[c] = (C)base[(8 + c) * P + cb];
-    }
-    C fL[4], gL[4], fR[4], gR[4];
-    fluxes(uL, K.gm1, fL, gL);
-    fluxes(uR, K.gm1, fR, gR);
-    C usx[4], dF[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const C d1 = maxw(0, uL[c], fL[c], gL[c], K.w, K.r2a) - u1L[c];
-      const C M2E = maxw(1, uR[c], fR[c], fR[c], K.w, K.r2a);
-      const C d2E = M2E - u2R[c];
-      usx[c] = C(0.5) * (uL[c] + uR[c]) - (fR[c] - fL[c]) * K.r2k;
-      dF[c] = K.ac * (d1 - d2E);
-    }
-    int guard;
-    const C zero = C(0);
-    double th = face_theta(sc, usx, dF, K.klim, zero, zero, zero, zero, guard);
-    if (sc.sponge > 0 && (in_sponge(sc, a, j, nx, ny) || in_sponge(sc, b, j, nx, ny))) th = 0.0;
-    A.edge[f] = th;
-    if (b >= 0 && b < nx) {
-      n_guard = (unsigned)guard;
-      n_lim = th < 1.0 ? 1u : 0u;
-    }
-    if (A.theta_x && b <= nx) A.theta_x[(long long)j * (nx + 1) + b] = th;
-  }
-  // one atomic per wave and instance (waves may straddle two instances)
-  const unsigned long long same = __ballot(ii == __shfl(ii, 0, 64));
-  if (same == ~0ull) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      n_guard += __shfl_xor(n_guard, off, 64);
-      n_lim += __shfl_xor(n_lim, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
-      if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
-    }
-  } else {
     if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
     if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
   }
@@ -880,13 +809,6 @@ hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
   const dim3 block(64 * a.waves_per_group);
   const dim3 grid(a.groups);
-  if (!lmp && a.n_edge > 0) {
-    const dim3 eg((unsigned)((a.n_edge + 255) / 256));
-    if (precision == 0)
-      hipLaunchKernelGGL((edge_kernel<double, double>), eg, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((edge_kernel<float, float>), eg, dim3(256), 0, s, a);
-  }
   if (precision == 0) {
     if (lmp)
       hipLaunchKernelGGL((step_kernel<double, double, true, VLBM_WPE_F64_LMP>), grid, block, 0, s, a);

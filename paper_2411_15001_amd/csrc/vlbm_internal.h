@@ -16,11 +16,9 @@ struct Scheme {
 struct Inst {
   long long off;   // element offset of cell (0, 0) inside every plane
   long long item0; // first work item (strip) of this instance
-  long long eoff;  // first entry of this instance in the strip-edge face table
   double dx;
   int nx, ny;
   int xs, ys;      // strips along x and y
-  int nk;          // strip-edge x-faces per row (full-width strips), or 0
 };
 
 // Per-instance device scalars.  lam and t rotate over three slots: step n
@@ -49,8 +47,6 @@ struct StepArgs {
   int groups;             // launched workgroups
   double* theta_x;        // optional face output (single instance)
   double* theta_y;
-  double* edge;           // theta of the x-faces on strip edges (full-width strips)
-  long long n_edge;       // entries of `edge`
   Scheme sc;
 };
 
