@@ -143,8 +143,20 @@ __device__ __forceinline__ double theta_p(double r0, double m1, double m2, doubl
   return vmax(0.0, kappa / r - eps);
 }
 
+// Margin of the division-free test below: c = 1 + 2^-30.
+constexpr double kFastMargin = 1.0 + 0x1p-30;
+
 // theta = min(1, selected theta^rho, theta^p) of one face (Section 3.2).  A
 // face state outside the admissible set takes the first-order value 0.
+//
+// Division-free shortcut, exact: theta^rho_PP = fl(fl(kappa rho*)/|D|) - eps
+// is >= 1 whenever fl(kappa rho*) >= fl(|D| c), and theta^p = fl(kappa/r) - eps
+// is >= 1 whenever, in addition, fl(N c) <= fl(kappa (-2 g0)) with
+// N = fl(|g1| + sqrt(Delta)) (both quotients behind r are then at most
+// kappa (1 + u)^2 / (c (1 - u)), u = 2^-53, and eps <= 1e-12 < 2^-32 cannot
+// bring a value above 1 + 2^-32 below 1).  In that case min(1, ...) over those
+// two limiters is exactly 1 and the four divisions are skipped; every other
+// lane evaluates the formulas in full, so the result is bit-identical.
 template <class C>
 __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], const C dF[4],
                                              double kappa, C muL, C nuL, C muR, C nuR,
@@ -159,16 +171,33 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
     return 0.0;
   }
   const double D = dF[0];
+  const bool fast_ok = s.eps <= 1e-12;
+  const bool fast_rho = fast_ok && (D == 0.0 || kappa * r0 >= fabs(D) * kFastMargin);
   double t = 1.0;
-  if (s.limiters & 1u) t = vmin(t, theta_rho_pp(r0, D, kappa, s.eps));
+  if ((s.limiters & 1u) && !fast_rho) t = vmin(t, theta_rho_pp(r0, D, kappa, s.eps));
   if (s.limiters & 2u)
     t = vmin(t, theta_rho_lmp(r0, D, kappa, (double)muL, (double)nuL, (double)muR, (double)nuR));
   if (s.limiters & 4u)
     t = vmin(t, theta_rho_lmp(r0, D, kappa, s.rlmp_lo * (double)muL, s.rlmp_hi * (double)nuL,
                               s.rlmp_lo * (double)muR, s.rlmp_hi * (double)nuR));
-  if (s.limiters & 8u)
-    t = vmin(t, theta_p(r0, m1, m2, E, D, (double)dF[1], (double)dF[2], (double)dF[3], kappa,
-                        s.eps));
+  if (s.limiters & 8u) {
+    const double Dm1 = dF[1], Dm2 = dF[2], DE = dF[3];
+    const double g1 = 2.0 * (D * E + DE * r0 - Dm1 * m1 - Dm2 * m2);
+    const double g2 = Dm1 * Dm1 + Dm2 * Dm2 - 2.0 * D * DE;
+    double disc = g1 * g1 - 4.0 * g0 * g2;
+    disc = vmax(0.0, disc);
+    const double N = fabs(g1) + sqrt(disc);
+    const double Dn = -2.0 * g0;
+    const bool fast_p = fast_rho && N * kFastMargin <= kappa * Dn;
+    if (!fast_p) {
+      // the expressions of theta_p, reusing g0, g1, disc, N and -2 g0
+      const double e1 = fabs(D) / r0;
+      const double e2 = N / Dn;
+      const double r = vmax(e1, e2);
+      const double tp = (r == 0.0) ? kHuge : vmax(0.0, kappa / r - s.eps);
+      t = vmin(t, tp);
+    }
+  }
   return t;
 }
 
