@@ -20,7 +20,7 @@ counters recorded under profiles/ (null if absent for this kernel build).
 
 cpu_baseline: the FP64 CPU oracle (OpenMP over rows, all host cores) timed on
 a bounded sample of the same workload: the blast on a 2048 x 2048 grid for
-40 steps (about 10-20 s of host time).
+80 steps (about 10-20 s of host time).
 """
 from __future__ import annotations
 
@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
