@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=80)
+    ap.add_argument("--workload", default="blast", choices=["blast", "rarefaction", "batch", "adjoint"],
+                    help="blast: the headline 8192^2 line; the others time the LMP, batching and "
+                         "differentiation forms on their own workloads")
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -149,6 +152,151 @@ def cpu_baseline(n, steps):
                       "OpenMP over rows" % (n, n, steps, dt)}
 
 
+def _timed(fn, steps):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, roofline, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": config, "roofline": roofline}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def bench_rarefaction(a):
+    """Near-vacuum double rarefaction 2048^2, FP64, PP + LMP + pressure,
+    outflow, a = 4 lambda (the LMP variant of the step)."""
+    import torch
+
+    from paper_2411_15001_amd import binding as B
+    from paper_2411_15001_amd import cases
+    from paper_2411_15001_amd.solver import Solver
+
+    n = 2048
+    s = Solver(cases.double_rarefaction(n, seed=0), limiters=B.LBM_RHO_PP | B.LBM_RHO_LMP | B.LBM_PRESSURE,
+               bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
+    if not a.no_autotune:
+        # tune on a developed flow (the limiters' slow paths are rare in the
+        # first steps), then restart from the initial state
+        init = s.get_state()
+        s.step(100)
+        s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
+        s.set_state(init)
+        s.moments(check=False)  # clears the event counters of the untimed steps
+        del init
+    s.step(a.warmup)
+    ms = _timed(lambda: s.step(a.steps), a.steps)
+    st = s.moments(check=False)[1]
+    avg = ms / a.steps
+    ach = 320.0 * n * n / (avg * 1e-3) / 1e9
+    _line(METRIC, n * n / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.warmup, avg, "f64",
+          {"workload": "near-vacuum double rarefaction 2048x2048, outflow, PP + LMP + pressure, "
+                       "a = 4 lambda, fp64 form", "grid": [n, n]},
+          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": None}, status=int(st),
+          launch=list(B.lbm_get_launch(s.ctx)))
+    s.close()
+
+
+def bench_batch(a):
+    """256 four-quadrant instances, side 128 k (k ~ U{1..8}), FP32 state, PP +
+    pressure, outflow, a = 4.4 lambda, one launch per step replayed from a
+    hipGraph of `steps` launches."""
+    import torch
+
+    from paper_2411_15001_amd import binding as B
+    from paper_2411_15001_amd import cases
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    sides = cases.batch_sides(256, seed=0)
+    u0s = cases.batch_riemann4(256, seed=0, sides=sides)
+    cells = sum(x * x for x in sides)
+    bs = BatchSolver(u0s, precision=B.LBM_FP32_STATE, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE,
+                     a_beta=1.1, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
+    del u0s
+    init = bs.get_state()
+    if not a.no_autotune:
+        bs.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
+    # capture and replay once (untimed), bring the slot phase back to the
+    # captured one, then restart from the initial state so that the timed
+    # replay is steps 0..steps-1 of the workload
+    bs.step_graph(a.steps)
+    bs.step((6 - a.steps % 6) % 6)
+    bs.set_state(init)
+    bs.moments(0, check=False)  # clears the event counters of the untimed pass
+    del init
+    torch.cuda.synchronize()
+    ms = _timed(lambda: bs.step_graph(a.steps), a.steps)
+    st = bs.moments(0, check=False)[1]
+    avg = ms / a.steps
+    ach = 160.0 * cells / (avg * 1e-3) / 1e9
+    _line(METRIC, cells / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.steps, avg,
+          "f32 (theta solve and CFL reduce f64)",
+          {"workload": "batch of 256 four-quadrant problems, sides 128k with k ~ U{1..8} (seed 0), "
+                       "fp32 state, PP + pressure, outflow, a = 4.4 lambda, hipGraph replay",
+           "instances": 256, "cells": cells},
+          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": None}, status=int(st),
+          launch=list(B.lbm_get_launch(bs.ctx)))
+    bs.close()
+
+
+def bench_adjoint(a):
+    """Gradient of the density misfit after 200 steps w.r.t. the initial state
+    (512^2 periodic Gaussian bump, FP64, fixed a, checkpoints every 20): one
+    forward + backward pass is the unit; reported as cell-steps/s of the
+    forward + adjoint rollout."""
+    import torch
+
+    from paper_2411_15001_amd import binding as B
+    from paper_2411_15001_amd import cases
+    from paper_2411_15001_amd.autograd import rollout
+    from paper_2411_15001_amd.solver import Solver
+
+    n, steps = 512, 200
+    u0 = cases.gaussian_bump(n, seed=0)
+    probe = Solver(u0)  # lambda^0 of the initial data, from the library
+    lam0 = probe.diagnostics()["lam"]
+    probe.close()
+    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=4.4 * lam0, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE)
+    t = Solver(cases.gaussian_bump_target(n), **kw)
+    t.step(steps)
+    rho_tgt = t.moments()[0].clone()
+    t.close()
+    u0t = torch.from_numpy(u0).cuda()
+
+    def once():
+        x = u0t.clone().requires_grad_(True)
+        m = rollout(x, steps, 20, **kw)
+        L = 0.5 * ((m[0] - rho_tgt) ** 2).sum()
+        L.backward()
+        return x.grad
+
+    for _ in range(max(1, a.warmup // 10)):
+        once()
+    reps = 3
+    ms = _timed(lambda: [once() for _ in range(reps)], reps) / reps
+    cell_steps = n * n * steps
+    _line("cell-steps/s of a forward + adjoint rollout (GLUPS)", cell_steps / (ms * 1e-3) / 1e9,
+          "GLUPS", steps, 0, ms / steps, "f64",
+          {"workload": "gradient of the density misfit after 200 steps w.r.t. u0, 512x512 periodic "
+                       "Gaussian bump, fixed a, checkpoints every 20", "grid": [n, n]},
+          {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+           "traffic": None}, ms_per_gradient=ms)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -156,6 +304,11 @@ def main():
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.workload != "blast":
+        torch.cuda.set_device(0)
+        {"rarefaction": bench_rarefaction, "batch": bench_batch, "adjoint": bench_adjoint}[a.workload](a)
+        return
 
     from paper_2411_15001_amd import cases
 

@@ -166,7 +166,9 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
  *   Ubar_n = (d S^{n+1} / d S^n)^T Ubar_np1.
  * All three are float64 states in the layout above (single instance,
  * LBM_FP64, periodic boundaries; LBM_ENOTSUP otherwise).  Uses the context's
- * workspace as scratch; does not change the context's own state. */
+ * workspace as scratch; does not change the context's own state.  Fully
+ * asynchronous on the context's stream (no host synchronisation); Ubar_n
+ * must not alias U_n or Ubar_np1, and U_n must not be a context buffer. */
 lbm_status lbm_step_adjoint(lbm_ctx* ctx, const double* U_n_dev,
                             const double* Ubar_np1_dev, double* Ubar_n_dev);
 
@@ -177,13 +179,19 @@ lbm_status lbm_init_adjoint(lbm_ctx* ctx, const double* u0_dev,
                             const double* Ubar0_dev, double* u0bar_dev);
 
 /* Times the step kernel for the candidate strip heights and waves per
- * workgroup on the context's own problem (advancing its state by the steps
- * it runs), keeps the fastest and records it in a JSON cache file keyed by
- * problem shape (NULL path = no file).  Synchronises. */
+ * workgroup on the context's own problem, keeps the fastest and records it in
+ * a JSON cache file keyed by problem shape (NULL path = no file); a cached
+ * entry is used without timing.  The timed launches read the current state
+ * and write the other buffer, and the slots (lambda, t, counters) are
+ * restored, so the context's state and step count are unchanged.
+ * Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
 
-/* Launch shape of the step kernel: rows per strip and waves per workgroup
- * (0 keeps the current value). */
+/* Launch shape of the step kernel: rows per strip in [4, 4096] and waves
+ * per workgroup in [1, 4] (0 keeps the current value; LBM_EINVAL outside
+ * those ranges).  A new context starts with 4 waves per workgroup and the
+ * tallest strip of 64, 32, 16, 8 or 4 rows that still yields at least 2048
+ * strips over all instances.  Changing the shape drops captured graphs. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t strip_rows, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* waves_per_group);
 

@@ -152,13 +152,30 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _require_cuda(t, dtype=None):
+def _require_cuda(t, dtype=None, numel=None, name="tensor"):
     import torch
 
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
-        raise ValueError("expected a contiguous device tensor")
+        raise ValueError("%s: expected a contiguous device tensor" % name)
     if dtype is not None and t.dtype != dtype:
-        raise ValueError("expected dtype %s, got %s" % (dtype, t.dtype))
+        raise ValueError("%s: expected dtype %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s: expected %d elements, got %d" % (name, numel, t.numel()))
+
+
+# (nx, ny) of every instance of each live context, keyed by the handle value;
+# the bindings check tensor sizes against it before a pointer reaches the
+# library (the C entry points take bare pointers).
+_shapes = {}
+
+
+def _inst_shape(ctx, inst=0):
+    sh = _shapes.get(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx)
+    if sh is None:
+        raise ValueError("unknown or destroyed context")
+    if not 0 <= inst < len(sh):
+        raise ValueError("instance index out of range")
+    return sh[inst]
 
 
 # --------------------------------------------------------------------------
@@ -179,19 +196,26 @@ def lbm_batch_workspace_bytes(params, nx, ny):
 def lbm_init(params, u0, workspace):
     import torch
 
-    _require_cuda(u0, torch.float64)
+    _require_cuda(u0, torch.float64, 4 * params.nx * params.ny, "u0")
     _require_cuda(workspace)
+    need = lbm_workspace_bytes(params)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace: %d bytes needed" % need)
     ctx = ctypes.c_void_p()
     _check(lib().lbm_init(ctypes.byref(params), _ptr(u0), _ptr(workspace), _stream(),
                           ctypes.byref(ctx)))
+    _shapes[ctx.value] = [(params.nx, params.ny)]
     return ctx
 
 
 def lbm_init_batch(params, nx, ny, u0_packed, workspace, dx=None):
     import torch
 
-    _require_cuda(u0_packed, torch.float64)
+    _require_cuda(u0_packed, torch.float64, 4 * sum(a * b for a, b in zip(nx, ny)), "u0_packed")
     _require_cuda(workspace)
+    need = lbm_batch_workspace_bytes(params, nx, ny)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace: %d bytes needed" % need)
     n = len(nx)
     ax = (ctypes.c_int32 * n)(*nx)
     ay = (ctypes.c_int32 * n)(*ny)
@@ -199,6 +223,7 @@ def lbm_init_batch(params, nx, ny, u0_packed, workspace, dx=None):
     ctx = ctypes.c_void_p()
     _check(lib().lbm_init_batch(ctypes.byref(params), n, ax, ay, adx, _ptr(u0_packed),
                                 _ptr(workspace), _stream(), ctypes.byref(ctx)))
+    _shapes[ctx.value] = [(int(a), int(b)) for a, b in zip(nx, ny)]
     return ctx
 
 
@@ -213,15 +238,17 @@ def lbm_step_graph(ctx, nsteps):
 def lbm_step_theta(ctx, theta_x, theta_y):
     import torch
 
-    _require_cuda(theta_x, torch.float64)
-    _require_cuda(theta_y, torch.float64)
+    nx, ny = _inst_shape(ctx)
+    _require_cuda(theta_x, torch.float64, ny * (nx + 1), "theta_x")
+    _require_cuda(theta_y, torch.float64, (ny + 1) * nx, "theta_y")
     return _check(lib().lbm_step_theta(ctx, _ptr(theta_x), _ptr(theta_y)), ctx)
 
 
 def lbm_moments(ctx, inst, out, check=True):
     import torch
 
-    _require_cuda(out, torch.float64)
+    nx, ny = _inst_shape(ctx, int(inst))
+    _require_cuda(out, torch.float64, 4 * nx * ny, "out")
     st = lib().lbm_moments(ctx, int(inst), _ptr(out))
     if check:
         _check(st, ctx)
@@ -238,29 +265,41 @@ def lbm_state_bytes(ctx):
     return lib().lbm_state_bytes(ctx)
 
 
+def _require_state_bytes(ctx, t):
+    need = lbm_state_bytes(ctx)
+    have = t.numel() * t.element_size()
+    if not t.is_contiguous() or have != need:
+        raise ValueError("state tensor must be contiguous and hold exactly %d bytes (got %d)"
+                         % (need, have))
+
+
 def lbm_get_state(ctx, dst):
     _require_cuda(dst)
+    _require_state_bytes(ctx, dst)
     return _check(lib().lbm_get_state(ctx, _ptr(dst)), ctx)
 
 
 def lbm_set_state(ctx, src):
     _require_cuda(src)
+    _require_state_bytes(ctx, src)
     return _check(lib().lbm_set_state(ctx, _ptr(src)), ctx)
 
 
 def lbm_step_adjoint(ctx, U_n, Ubar_np1, Ubar_n):
     import torch
 
-    for t in (U_n, Ubar_np1, Ubar_n):
-        _require_cuda(t, torch.float64)
+    nx, ny = _inst_shape(ctx)
+    for t, name in ((U_n, "U_n"), (Ubar_np1, "Ubar_np1"), (Ubar_n, "Ubar_n")):
+        _require_cuda(t, torch.float64, 20 * nx * ny, name)
     return _check(lib().lbm_step_adjoint(ctx, _ptr(U_n), _ptr(Ubar_np1), _ptr(Ubar_n)), ctx)
 
 
 def lbm_init_adjoint(ctx, u0, Ubar0, u0bar):
     import torch
 
-    for t in (u0, Ubar0, u0bar):
-        _require_cuda(t, torch.float64)
+    nx, ny = _inst_shape(ctx)
+    for t, name, k in ((u0, "u0", 4), (Ubar0, "Ubar0", 20), (u0bar, "u0bar", 4)):
+        _require_cuda(t, torch.float64, k * nx * ny, name)
     return _check(lib().lbm_init_adjoint(ctx, _ptr(u0), _ptr(Ubar0), _ptr(u0bar)), ctx)
 
 
@@ -285,4 +324,5 @@ def lbm_last_error(ctx=None):
 
 
 def lbm_destroy(ctx):
+    _shapes.pop(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx, None)
     lib().lbm_destroy(ctx)

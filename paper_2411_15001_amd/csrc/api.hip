@@ -17,7 +17,7 @@ using vlbm::Slots;
 
 namespace {
 
-constexpr int kMinStripRows = 16;  // bounds the work-item table in the workspace
+constexpr int kMinStripRows = 4;  // bounds the work-item table in the workspace
 constexpr int kMaxStripRows = 4096;
 constexpr size_t kAlign = 256;
 
@@ -86,7 +86,7 @@ Scheme make_scheme(const lbm_params* p) {
 }
 
 struct Layout {
-  size_t slots, insts, items, bufA, bufB, theta, total;
+  size_t slots, slots_save, insts, items, bufA, bufB, theta, total;
 };
 
 Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
@@ -101,6 +101,8 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   size_t o = 0;
   L.slots = o;
   o = align_up(o + sizeof(Slots) * (size_t)n);
+  L.slots_save = o;  // the adjoint entry points park the slots here
+  o = align_up(o + sizeof(Slots));
   L.insts = o;
   o = align_up(o + sizeof(Inst) * (size_t)n);
   L.items = o;
@@ -176,6 +178,23 @@ void build_items(lbm_ctx* c) {
       for (long long q = 0; q < k; ++q) c->item_inst.push_back(i);
     c->n_items += k;
   }
+}
+
+// Default strip height: the tallest of 64, 32, 16, 8, 4 rows that still
+// yields at least kDefaultItems strips (one wave each), so that small grids
+// are cut into enough waves to cover the chip while large ones keep the
+// one-row overlap per strip small.  lbm_autotune refines it.
+constexpr long long kDefaultItems = 2048;
+
+int default_strip_rows(const lbm_ctx* c) {
+  const int R = halo_radius(&c->p);
+  int rows = 64;
+  for (; rows > kMinStripRows; rows /= 2) {
+    long long items = 0;
+    for (const Inst& in : c->insts) items += strips_x(in.nx, R) * strips_y(in.ny, rows);
+    if (items >= kDefaultItems) break;
+  }
+  return rows;
 }
 
 lbm_status upload_tables(lbm_ctx* c) {
@@ -298,6 +317,7 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     c->persistent_groups = cus * 4;
   }
+  c->strip_rows = default_strip_rows(c);
   build_items(c);
   lbm_status st = upload_tables(c);
   if (st != LBM_OK) {
@@ -525,7 +545,7 @@ lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const double* Ub0, dou
 lbm_status lbm_set_launch(lbm_ctx* c, int32_t rows, int32_t waves) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (rows != 0 && (rows < kMinStripRows || rows > kMaxStripRows))
-    return fail(c, LBM_EINVAL, "strip rows must lie in [16, 4096]");
+    return fail(c, LBM_EINVAL, "strip rows must lie in [4, 4096]");
   if (waves != 0 && (waves < 1 || waves > 4)) return fail(c, LBM_EINVAL, "waves per group must lie in [1, 4]");
   if (rows) c->strip_rows = rows;
   if (waves) c->waves = waves;
@@ -569,7 +589,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   std::vector<Slots> saved;
   lbm_status st = read_slots(c, saved);
   if (st != LBM_OK) return st;
-  const int rows_c[] = {16, 32, 64, 128, 256};
+  const int rows_c[] = {4, 8, 16, 32, 64, 128, 256};
   const int waves_c[] = {1, 2, 4};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -584,14 +604,22 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
       // time launches that all read the current state and write the other
       // buffer (the state is not advanced)
       vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
-      const int reps = 4;
+      // one timed launch sizes the repetition count to about 4 ms of work
       hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
       if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-      for (int k = 0; k < reps && e == hipSuccess; ++k) e = vlbm::launch_step(a, c->p.precision, c->stream);
+      if (e == hipSuccess) e = vlbm::launch_step(a, c->p.precision, c->stream);
       if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      int reps = ms > 0.0f ? (int)(4.0f / ms) : 64;
+      reps = reps < 2 ? 2 : (reps > 64 ? 64 : reps);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) e = vlbm::launch_step(a, c->p.precision, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) ms /= reps;
       if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -686,10 +714,11 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double
   if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
   // theta^n of U with the forward kernel (its state output goes to the
   // context's other buffer, which the next forward step overwrites anyway;
-  // the counters it adds are restored below)
-  std::vector<Slots> saved;
-  lbm_status st = read_slots(c, saved);
-  if (st != LBM_OK) return st;
+  // the slots it touches are parked and restored on the stream, no host
+  // round trip)
+  Slots* save = (Slots*)(c->ws + c->lay.slots_save);
+  e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint slot save");
   vlbm::StepArgs a = make_args(c, U, c->other(), scratch);
   a.theta_x = tx;
   a.theta_y = ty;
@@ -699,7 +728,9 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double
                                 c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   // restore the scalar slots (lambda, t, counters) of the forward run
-  return write_slots(c, saved);
+  e = hipMemcpyAsync(c->slots, save, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint slot restore");
+  return LBM_OK;
 }
 
 extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const double* Ub0,
@@ -708,17 +739,19 @@ extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const doubl
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
   if (!u0 || !Ub0 || !u0b) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
-  std::vector<Slots> saved;
-  lbm_status st = read_slots(c, saved);
-  if (st != LBM_OK) return st;
+  Slots* save = (Slots*)(c->ws + c->lay.slots_save);
+  hipError_t e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "init adjoint slot save");
   // lambda^0 of u0 into a scratch slot
   const int scratch = (int)((c->step + 2) % 3);
-  hipError_t e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
+  e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, (long long)c->insts[0].nx * c->insts[0].ny,
                                   u0, c->slots, scratch, LBM_FP64, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_adjoint_init(c->sc, c->insts[0], u0, Ub0, u0b, c->slots, scratch, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "init adjoint launch");
-  return write_slots(c, saved);
+  e = hipMemcpyAsync(c->slots, save, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "init adjoint slot restore");
+  return LBM_OK;
 }

@@ -203,6 +203,27 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
 
 // Wavespeed |v| + sqrt(gamma p / rho) of one state, or -1 if it is not
 // admissible (rho <= 0, p <= 0 or a non-finite result).
+// Raise lambda slot `slot` to at least lmax (>= 0; the bit patterns of
+// non-negative doubles order like the integers).  Within one step a slot only
+// grows from the zero the previous step stored, so an agent-scope read that
+// already shows lmax or more makes the read-modify-write redundant: most
+// waves skip it, which keeps same-address atomics off the critical path of
+// short launches.
+__device__ __forceinline__ void raise_lambda(unsigned long long* p, double lmax) {
+  const unsigned long long v = (unsigned long long)__double_as_longlong(lmax);
+  const unsigned long long seen = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v > seen) atomicMax(p, v);
+}
+
+// One lane per wave publishes the wave's wavespeed maximum and event counts.
+__device__ __forceinline__ void publish(Slots* sl, int slot, double lmax, unsigned n_bad,
+                                       unsigned n_guard, unsigned n_lim) {
+  raise_lambda(&sl->lam[slot], lmax);
+  if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
+  if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
+  if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+}
+
 __device__ __forceinline__ double cell_wavespeed(double rho, double m1, double m2, double E,
                                                  double gamma) {
   const double ir = 1.0 / rho;
@@ -484,12 +505,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     n_guard += __shfl_xor(n_guard, off, 64);
     n_lim += __shfl_xor(n_lim, off, 64);
   }
-  if (lane == 0) {
-    atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
-    if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
-    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
-    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
-  }
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim);
 }
 
 // One strip: columns x0 .. x0 + 63, output rows [y0, y1).
@@ -695,12 +711,7 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
     n_guard += __shfl_xor(n_guard, off, 64);
     n_lim += __shfl_xor(n_lim, off, 64);
   }
-  if (lane == 0) {
-    atomicMax(&sl->lam[(A.slot + 1) % 3], (unsigned long long)__double_as_longlong(lmax));
-    if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
-    if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
-    if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
-  }
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim);
 }
 
 template <class T, class C, bool LMP, int WPE>
@@ -762,8 +773,20 @@ __global__ __launch_bounds__(256) void lambda_kernel(const Src* __restrict__ u, 
     lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
     bad += __shfl_xor(bad, off, 64);
   }
+  // block reduction (every thread of the block reaches the barrier), then one
+  // update per block
+  __shared__ double wl[4];
+  __shared__ unsigned wb[4];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&sl->lam[slot], (unsigned long long)__double_as_longlong(lmax));
+    wl[w] = lmax;
+    wb[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lmax = vmax(vmax(wl[0], wl[1]), vmax(wl[2], wl[3]));
+    bad = wb[0] + wb[1] + wb[2] + wb[3];
+    raise_lambda(&sl->lam[slot], lmax);
     if (bad) atomicAdd(&sl->cnt[CNT_BAD], bad);
   }
 }
@@ -825,12 +848,16 @@ __global__ void fill_f64_kernel(double* p, double v, long long n) {
 #define VLBM_WPE_F32_LMP 2
 #endif
 
-int grid_for(long long n) {
+int grid_for(long long n, long long cap = 8192) {
   long long g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
+  if (g > cap) g = cap;
   if (g < 1) g = 1;
   return (int)g;
 }
+
+// Reductions: a few blocks per CU, each thread striding over many cells, so
+// that few block results meet at the slot.
+int grid_for_reduce(long long n) { return grid_for(n, 1024); }
 
 }  // namespace
 
@@ -861,10 +888,10 @@ hipError_t launch_init(const Scheme& sc, const Inst* insts, int n_inst, const In
     const long long n = (long long)in.nx * in.ny;
     const double* u = u0 + u0_off;
     if (precision == 0)
-      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u,
+      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for_reduce(n)), dim3(256), 0, s, u,
                          n, n, sc.gamma, slots + i, 0);
     else
-      hipLaunchKernelGGL((lambda_kernel<double, float>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
+      hipLaunchKernelGGL((lambda_kernel<double, float>), dim3(grid_for_reduce(n)), dim3(256), 0, s, u, n,
                          n, sc.gamma, slots + i, 0);
     if (precision == 0)
       hipLaunchKernelGGL((init_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
@@ -884,10 +911,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts, int n_inst, 
     const Inst& in = insts[i];
     const long long n = (long long)in.nx * in.ny;
     if (precision == 0)
-      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s,
+      hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
                          (const double*)S + in.off, plane, n, sc.gamma, slots + i, slot);
     else
-      hipLaunchKernelGGL((lambda_kernel<float, float>), dim3(grid_for(n)), dim3(256), 0, s,
+      hipLaunchKernelGGL((lambda_kernel<float, float>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
                          (const float*)S + in.off, plane, n, sc.gamma, slots + i, slot);
   }
   return hipGetLastError();

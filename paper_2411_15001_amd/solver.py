@@ -115,6 +115,17 @@ class BatchSolver:
     def step_graph(self, n):
         B.lbm_step_graph(self.ctx, n)
 
+    def get_state(self):
+        """Copy of the whole ensemble's state buffer (opaque bytes)."""
+        import torch
+
+        s = torch.empty(B.lbm_state_bytes(self.ctx), dtype=torch.uint8, device="cuda")
+        B.lbm_get_state(self.ctx, s)
+        return s
+
+    def set_state(self, s):
+        B.lbm_set_state(self.ctx, s.contiguous())
+
     def moments(self, inst, check=True):
         import torch
 
