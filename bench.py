@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-updates/s (GLUPS) + % HBM roofline, FP64 vs FP32 form, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"fp32": 160.0, "fp64": 320.0}
-PMC_FILE = os.path.join(ROOT, "profiles", "traffic_step_blast8192.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "traffic_step.json")
 
 
 def parse():
@@ -114,9 +114,10 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     }
 
 
-def traffic_for(form):
-    """Measured HBM bytes per launch (rocprofv3 counters), if recorded for the
-    current library build."""
+def traffic_for(key):
+    """Measured HBM bytes per launch (rocprofv3 counters) of the workload and
+    form `key` (e.g. "blast8192_fp32"), if recorded for the current kernel
+    source."""
     try:
         with open(PMC_FILE) as f:
             rec = json.load(f)
@@ -129,7 +130,7 @@ def traffic_for(form):
     for name in ("step.hip", "vlbm_internal.h"):
         with open(os.path.join(ROOT, "paper_2411_15001_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    entry = rec.get(form)
+    entry = rec.get(key)
     if not entry or entry.get("source_sha256") != h.hexdigest() or not os.path.exists(lib):
         return None
     return entry.get("bytes_per_launch")
@@ -205,8 +206,8 @@ def bench_rarefaction(a):
           {"workload": "near-vacuum double rarefaction 2048x2048, outflow, PP + LMP + pressure, "
                        "a = 4 lambda, fp64 form", "grid": [n, n]},
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": None}, status=int(st),
-          launch=list(B.lbm_get_launch(s.ctx)))
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("rarefaction%d_fp64" % n)},
+          status=int(st), launch=list(B.lbm_get_launch(s.ctx)))
     s.close()
 
 
@@ -319,7 +320,7 @@ def main():
     forms = {}
     for form in a.forms.split(","):
         forms[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
-        forms[form]["roofline"]["traffic"] = traffic_for(form)
+        forms[form]["roofline"]["traffic"] = traffic_for("blast%d_%s" % (a.n, form))
         print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
             form, forms[form]["value"], forms[form]["ms_per_step"],
             100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)

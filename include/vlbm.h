@@ -190,8 +190,9 @@ lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
 /* Launch shape of the step kernel: rows per strip in [4, 4096] and waves
  * per workgroup in [1, 4] (0 keeps the current value; LBM_EINVAL outside
  * those ranges).  A new context starts with 4 waves per workgroup and the
- * tallest strip of 64, 32, 16, 8 or 4 rows that still yields at least 2048
- * strips over all instances.  Changing the shape drops captured graphs. */
+ * tallest strip of 64, 32, 16, 8 or 4 rows that still yields at least 1024
+ * (LBM_FP64) or 2048 (LBM_FP32_STATE) strips over all instances.  Changing
+ * the shape drops captured graphs. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t strip_rows, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* waves_per_group);
 

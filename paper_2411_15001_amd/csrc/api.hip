@@ -25,18 +25,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 thread_local std::string g_init_error;
 
-bool uses_bounds(const lbm_params* p) {
-  return p->order == 2 && (p->limiters & (LBM_RHO_LMP | LBM_RHO_RLMP));
-}
-
-// Lanes of a 64-wide strip that only supply neighbours: 2 on each side when
-// the density bounds are needed, none otherwise (full-width strips).
-int halo_radius(const lbm_params* p) { return uses_bounds(p) ? 2 : 0; }
-
-long long strips_x(int nx, int R) {
-  const int ow = 64 - 2 * R;
-  return (nx + ow - 1) / ow;
-}
+// Strips are 64 columns wide and aligned (every lane produces its column;
+// the edge lanes read the halo columns themselves).
+long long strips_x(int nx) { return (nx + 63) / 64; }
 
 long long strips_y(int ny, int h) { return (ny + h - 1) / h; }
 
@@ -91,11 +82,10 @@ struct Layout {
 
 Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   const size_t elem = p->precision == LBM_FP64 ? 8 : 4;
-  const int R = halo_radius(p);
   long long cells = 0, items = 0;
   for (int i = 0; i < n; ++i) {
     cells += (long long)nx[i] * ny[i];
-    items += strips_x(nx[i], R) * strips_y(ny[i], kMinStripRows);
+    items += strips_x(nx[i]) * strips_y(ny[i], kMinStripRows);
   }
   Layout L;
   size_t o = 0;
@@ -165,12 +155,11 @@ lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
 
 // Rebuild the strip tables after a change of strip height.
 void build_items(lbm_ctx* c) {
-  const int R = halo_radius(&c->p);
   c->n_items = 0;
   c->item_inst.clear();
   for (int i = 0; i < c->n_inst; ++i) {
     Inst& in = c->insts[i];
-    in.xs = (int)strips_x(in.nx, R);
+    in.xs = (int)strips_x(in.nx);
     in.ys = (int)strips_y(in.ny, c->strip_rows);
     in.item0 = c->n_items;
     const long long k = (long long)in.xs * in.ys;
@@ -181,18 +170,17 @@ void build_items(lbm_ctx* c) {
 }
 
 // Default strip height: the tallest of 64, 32, 16, 8, 4 rows that still
-// yields at least kDefaultItems strips (one wave each), so that small grids
-// are cut into enough waves to cover the chip while large ones keep the
-// one-row overlap per strip small.  lbm_autotune refines it.
-constexpr long long kDefaultItems = 2048;
-
+// yields one full round of strips (one wave each) over the chip's 1024 SIMDs
+// at the step kernel's occupancy (1 wave per SIMD in float64, 2 with the
+// float32 state), so that small grids are cut into enough waves while large
+// ones keep the re-read halo rows per strip few.  lbm_autotune refines it.
 int default_strip_rows(const lbm_ctx* c) {
-  const int R = halo_radius(&c->p);
+  const long long want = c->p.precision == LBM_FP64 ? 1024 : 2048;
   int rows = 64;
   for (; rows > kMinStripRows; rows /= 2) {
     long long items = 0;
-    for (const Inst& in : c->insts) items += strips_x(in.nx, R) * strips_y(in.ny, rows);
-    if (items >= kDefaultItems) break;
+    for (const Inst& in : c->insts) items += strips_x(in.nx) * strips_y(in.ny, rows);
+    if (items >= want) break;
   }
   return rows;
 }

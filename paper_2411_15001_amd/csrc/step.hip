@@ -123,8 +123,15 @@ __device__ __forceinline__ double theta_rho_pp(double rs, double D, double kappa
 __device__ __forceinline__ double theta_rho_lmp(double rs, double D, double kappa, double muL,
                                                 double nuL, double muR, double nuR) {
   if (D == 0.0) return 1.0;
-  if (D > 0.0) return kappa * vmin(nuR - rs, rs - muL) / D;
-  return -kappa * vmin(rs - muR, nuL - rs) / D;
+  // the caller takes min(1, .): when the dividend already reaches D (in the
+  // direction of its sign) the rounded quotient is >= 1, and 1 stands in for
+  // it without the division
+  if (D > 0.0) {
+    const double num = kappa * vmin(nuR - rs, rs - muL);
+    return num >= D ? 1.0 : num / D;
+  }
+  const double num = -kappa * vmin(rs - muR, nuL - rs);
+  return num <= D ? 1.0 : num / D;
 }
 
 // Section 3.4: kappa over the spectral radius of B^{-1/2} A B^{-1/2}
@@ -201,8 +208,6 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
   return t;
 }
 
-// Wavespeed |v| + sqrt(gamma p / rho) of one state, or -1 if it is not
-// admissible (rho <= 0, p <= 0 or a non-finite result).
 // Raise lambda slot `slot` to at least lmax (>= 0; the bit patterns of
 // non-negative doubles order like the integers).  Within one step a slot only
 // grows from the zero the previous step stored, so an agent-scope read that
@@ -224,6 +229,8 @@ __device__ __forceinline__ void publish(Slots* sl, int slot, double lmax, unsign
   if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
 }
 
+// Wavespeed |v| + sqrt(gamma p / rho) of one state, or -1 if it is not
+// admissible (rho <= 0, p <= 0 or a non-finite result).
 __device__ __forceinline__ double cell_wavespeed(double rho, double m1, double m2, double E,
                                                  double gamma) {
   const double ir = 1.0 / rho;
@@ -508,19 +515,29 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim);
 }
 
-// One strip: columns x0 .. x0 + 63, output rows [y0, y1).
-template <class T, class C, bool LMP>
-__device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* sl, int xs, int ys,
-                                      int lane) {
-  constexpr int R = LMP ? 2 : 1;
-  constexpr int OW = 64 - 2 * R;
+// One aligned strip of the bounds-limited scheme (LMP / RLMP, eq. (29)):
+// columns x0 .. x0 + 63, output rows [y0, y1).  A face's theta needs the
+// density bounds of both its cells, and a cell's bounds need its upper y-face,
+// so row L - 1's faces get their theta when row L arrives and row L - 2
+// completes then (rows y0 - 2 .. y1 + 1 are read).  The edge lanes look one
+// cell further out: lane 0 loads the west halo column x0 - 1 (u, u_1) and
+// rho, m_1 of x0 - 2; lane 63 loads the east halo column x0 + 64 (u, u_2) and
+// rho, m_1 of x0 + 65.  From them each evaluates the bounds of its halo cell,
+// and lane 0 the west edge face x0 - 1/2, with the same expressions as every
+// other lane, so both strips beside an edge face see the same theta.
+template <class T, class C>
+__device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slots* sl, int xs,
+                                          int ys, int lane) {
   const Scheme& sc = A.sc;
   const int nx = in.nx, ny = in.ny;
-  const int x0 = xs * OW - R;
+  const int x0 = xs * 64;
   const int gi = x0 + lane;
   const int ci = map_index(gi, nx, sc.bc_x);
-  const bool lane_out = lane >= R && lane < 64 - R && gi < nx;
-  const bool right_out = lane + 1 >= R && lane + 1 < 64 - R && gi + 1 < nx && gi + 1 >= 0;
+  const bool lane_out = gi < nx;
+  const bool first = lane == 0, last = lane == 63;
+  const int hcol = first ? map_index(x0 - 1, nx, sc.bc_x) : map_index(x0 + 64, nx, sc.bc_x);
+  const int ocol = first ? map_index(x0 - 2, nx, sc.bc_x) : map_index(x0 + 65, nx, sc.bc_x);
+  const int hslot = first ? 4 : 8;
   const int y0 = ys * A.strip_h;
   const int y1 = min(y0 + A.strip_h, ny);
   const bool sponge = sc.sponge > 0;
@@ -529,15 +546,15 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
 
   if (xs == 0 && ys == 0 && lane == 0) {
-    // rotate the scalar slots (this instance's first strip does it)
     sl->lam[(A.slot + 2) % 3] = 0ull;
     sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
     if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
   }
 
-  const T* __restrict__ src = (const T*)A.src + in.off + ci;
-  T* __restrict__ dst = (T*)A.dst + in.off + gi;
+  const T* __restrict__ sbase = (const T*)A.src + in.off;
+  T* __restrict__ dbase = (T*)A.dst + in.off;
   const long long P = A.plane;
+  const unsigned unx = (unsigned)nx;
 
   // carried state (zero before the first rows arrive)
   C pu[4] = {}, pf[4] = {}, pg[4] = {}, puk[4][4] = {};  // row L - 1
@@ -545,45 +562,78 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
   C pusy[4] = {}, pdG[4] = {};                          // y-face L - 3/2
   C pmu = C(0), pnu = C(0);                             // bounds of row L - 2
   C qM3[4] = {}, qd3[4] = {}, qP[4] = {};               // row L - 2
+  // edge lanes: the halo column's u and u_1 / u_2 of row L - 1, rho and m_1
+  // of the outer column in row L - 1, the halo cell's y-face density at L - 3/2
+  C hpu[4] = {}, hpk[4] = {};
+  C opr = C(0), opm = C(0), hpy = C(0);
 
   double lmax = 0.0;
   unsigned n_bad = 0, n_guard = 0, n_lim = 0;
 
-  T raw[20];
+  T raw[20], hraw[8] = {}, oraw[2] = {};
   {
-    const int cj = map_index(y0 - 2, ny, sc.bc_y);
-    const T* s = src + (long long)cj * nx;
+    const unsigned ro = (unsigned)map_index(y0 - 2, ny, sc.bc_y) * unx;
+    const unsigned o = ro + (unsigned)ci;
 #pragma unroll
-    for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+    if (first || last) {
+      const unsigned oh = ro + (unsigned)hcol;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
+      const unsigned oo = ro + (unsigned)ocol;
+      oraw[0] = sbase[oo];
+      oraw[1] = (sbase + P)[oo];
+    }
   }
 
   for (int L = y0 - 2; L <= y1 + 1; ++L) {
-    C u[4], uk[4][4];
+    C u[4], uk[4][4], hu[4], hk[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = (C)raw[c];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int c = 0; c < 4; ++c) uk[k][c] = (C)raw[4 + 4 * k + c];
-    if (L <= y1) {  // prefetch row L + 1
-      const int cj = map_index(L + 1, ny, sc.bc_y);
-      const T* s = src + (long long)cj * nx;
 #pragma unroll
-      for (int q = 0; q < 20; ++q) raw[q] = s[q * P];
+    for (int c = 0; c < 4; ++c) {
+      hu[c] = (C)hraw[c];
+      hk[c] = (C)hraw[4 + c];
+    }
+    const C orr = (C)oraw[0], om = (C)oraw[1];
+    if (L <= y1) {  // prefetch row L + 1
+      const unsigned ro = (unsigned)map_index(L + 1, ny, sc.bc_y) * unx;
+      const unsigned o = ro + (unsigned)ci;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+      if (first || last) {
+        const unsigned oh = ro + (unsigned)hcol;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hraw[q] = (sbase + q * P)[oh];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hraw[4 + q] = (sbase + (hslot + q) * P)[oh];
+        const unsigned oo = ro + (unsigned)ocol;
+        oraw[0] = sbase[oo];
+        oraw[1] = (sbase + P)[oo];
+      }
     }
 
-    // ---- row L: fluxes, Maxwellians, faces
+    // ---- row L: fluxes, the x-face i+1/2 and the y-face L - 1/2
     C f[4], g[4];
     fluxes(u, K.gm1, f, g);
+    C hf[4], hg[4];
+    fluxes(hu, K.gm1, hf, hg);
     C usx[4], dF[4], usy[4], dG[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const C d1 = maxw(0, u[c], f[c], g[c], K.w, K.r2a) - uk[0][c];
-      const C d2 = maxw(1, u[c], f[c], g[c], K.w, K.r2a) - uk[1][c];
       const C d4 = maxw(3, u[c], f[c], g[c], K.w, K.r2a) - uk[3][c];
-      const C uE = from_right(u[c]);
-      const C fE = from_right(f[c]);
-      const C d2E = from_right(d2);
+      // lanes 0..62 take lane + 1; lane 63 takes its halo (the east column)
+      const C uE = from_right_or(u[c], hu[c]);
+      const C fE = from_right_or(f[c], hf[c]);
+      const C u2E = from_right_or(uk[1][c], hk[c]);
+      const C d2E = maxw(1, uE, fE, fE, K.w, K.r2a) - u2E;
       usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
       dF[c] = K.ac * (d1 - d2E);
       const C pd3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a) - puk[2][c];
@@ -591,34 +641,69 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
       dG[c] = K.ac * (pd3 - d4);
     }
 
-    // ---- row L - 1: density bounds (eq. (29)), faces' theta
-    C mu1 = C(0), nu1 = C(0);
-    if (LMP) {
-      const C rW = from_left(pusx[0]);
-      C lo = pu[0], hi = pu[0];
-      lo = vmin(lo, rW);
-      hi = vmax(hi, rW);
-      lo = vmin(lo, pusx[0]);
-      hi = vmax(hi, pusx[0]);
-      lo = vmin(lo, pusy[0]);
-      hi = vmax(hi, pusy[0]);
-      lo = vmin(lo, usy[0]);
-      hi = vmax(hi, usy[0]);
-      mu1 = lo;
-      nu1 = hi;
+    // ---- row L - 1: the halo column's Maxwellians, the west edge face
+    C hpf[4], hpg[4];
+    fluxes(hpu, K.gm1, hpf, hpg);
+    C hM[4], hd[4], usw[4], dFw[4], pd2[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      // lane 0: M_1 of the west column; lane 63: M_2 of the east column
+      const C hM1 = maxw(0, hpu[c], hpf[c], hpg[c], K.w, K.r2a);
+      const C hM2 = maxw(1, hpu[c], hpf[c], hpg[c], K.w, K.r2a);
+      hM[c] = first ? hM1 : hM2;
+      hd[c] = hM[c] - hpk[c];
+      pd2[c] = maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a) - puk[1][c];
+      usw[c] = C(0.5) * (hpu[c] + pu[c]) - (pf[c] - hpf[c]) * K.r2k;
+      dFw[c] = K.ac * (hd[c] - pd2[c]);
     }
-    const C muE = from_right(mu1);
-    const C nuE = from_right(nu1);
-    int gx, gy;
+
+    // ---- row L - 1: density bounds (eq. (29)) of the own cell and of the
+    // halo cell (edge lanes)
+    const C rW = from_left_or(pusx[0], usw[0]);
+    C mu1 = pu[0], nu1 = pu[0];
+    mu1 = vmin(mu1, rW);
+    nu1 = vmax(nu1, rW);
+    mu1 = vmin(mu1, pusx[0]);
+    nu1 = vmax(nu1, pusx[0]);
+    mu1 = vmin(mu1, pusy[0]);
+    nu1 = vmax(nu1, pusy[0]);
+    mu1 = vmin(mu1, usy[0]);
+    nu1 = vmax(nu1, usy[0]);
+    // halo cell: its inner x-face (lane 0: the west edge face; lane 63: its
+    // own east face), its outer x-face and its y-faces L - 3/2 and L - 1/2
+    const C xin = first ? usw[0] : pusx[0];
+    const C rwo = first ? opr : hpu[0], rwe = first ? hpu[0] : opr;
+    const C mwo = first ? opm : hpu[1], mwe = first ? hpu[1] : opm;
+    const C xout = C(0.5) * (rwo + rwe) - (mwe - mwo) * K.r2k;
+    const C hy = C(0.5) * (hpu[0] + hu[0]) - (hu[2] - hpu[2]) * K.r2k;
+    C hmu = hpu[0], hnu = hpu[0];
+    hmu = vmin(hmu, first ? xout : xin);
+    hnu = vmax(hnu, first ? xout : xin);
+    hmu = vmin(hmu, first ? xin : xout);
+    hnu = vmax(hnu, first ? xin : xout);
+    hmu = vmin(hmu, hpy);
+    hnu = vmax(hnu, hpy);
+    hmu = vmin(hmu, hy);
+    hnu = vmax(hnu, hy);
+
+    // ---- theta of the x-face i+1/2 and the west edge face of row L - 1,
+    // and of the y-face L - 3/2
+    const C muE = from_right_or(mu1, hmu);
+    const C nuE = from_right_or(nu1, hnu);
+    int gx, gy, gw;
     double thx = face_theta(sc, pusx, pdF, K.klim, mu1, nu1, muE, nuE, gx);
     double thy = face_theta(sc, pusy, pdG, K.klim, pmu, pnu, mu1, nu1, gy);
+    double th_edge = face_theta(sc, usw, dFw, K.klim, hmu, hnu, mu1, nu1, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi + 1, L - 1, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 2, nx, ny) || in_sponge(sc, gi, L - 1, nx, ny)) thy = 0.0;
+      if (in_sponge(sc, x0 - 1, L - 1, nx, ny) || in_sponge(sc, x0, L - 1, nx, ny)) th_edge = 0.0;
     }
     const bool row1 = L - 1 >= y0 && L - 1 < y1;  // row L - 1 is produced by this strip
     const bool row2 = L - 2 >= y0 && L - 2 < y1;  // row L - 2 is completed now
-    if (row1 && right_out) {
+    // faces counted here: the x-face i+1/2 of lanes 0..62, the west edge
+    // face (lane 0) and the y-face L - 3/2 of every lane
+    if (row1 && !last && gi + 1 < nx) {
       n_guard += gx;
       n_lim += (thx < 1.0);
     }
@@ -626,53 +711,53 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
       n_guard += gy;
       n_lim += (thy < 1.0);
     }
+    if (row1 && first) {
+      n_guard += gw;
+      n_lim += (th_edge < 1.0);
+    }
     if (A.theta_x) {
-      const int fi = gi + 1;
-      if (row1 && (lane_out || right_out) && fi >= 0 && fi <= nx)
-        A.theta_x[(long long)(L - 1) * (nx + 1) + fi] = thx;
+      if (row1 && first) A.theta_x[(long long)(L - 1) * (nx + 1) + x0] = th_edge;
+      if (row1 && gi + 1 <= nx) A.theta_x[(long long)(L - 1) * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row1 || row2) && L - 1 >= 0 && L - 1 <= ny)
         A.theta_y[(long long)(L - 1) * nx + gi] = thy;
     }
 
     // ---- rows L - 1 and L - 2: streaming and the moment slot (eqs. (25), (27))
     const C tR = (C)thx;
-    const C tL = from_left(tR);
+    const C tL = from_left_or(tR, (C)th_edge);  // lane 0: the west edge face
     const C tB = (C)thy;
     C fin[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const C pM1 = maxw(0, pu[c], pf[c], pg[c], K.w, K.r2a);
-      const C pM2 = maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a);
       const C pM3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a);
       const C pM4 = maxw(3, pu[c], pf[c], pg[c], K.w, K.r2a);
       const C pd1 = pM1 - puk[0][c];
-      const C pd2 = pM2 - puk[1][c];
       const C pd4 = pM4 - puk[3][c];
-      const C M1W = from_left(pM1);
-      const C d1W = from_left(pd1);
-      const C M2E = from_right(pM2);
-      const C d2E = from_right(pd2);
-      // row L - 1: faces i-1/2, i+1/2 and j-1/2 (= L - 3/2)
-      const C u1n = M1W + tL * d1W;
+      // M_1 + theta d_1 of the west neighbour (lane 0: the halo column)
+      const C u1n = from_left_or(pM1 + tR * pd1, hM[c] + tL * hd[c]);
+      // M_2 + theta d_2 of the east neighbour (lane 63: the halo column)
+      const C M2E = from_right_or(maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a), hM[c]);
+      const C d2E = from_right_or(pd2[c], hd[c]);
       const C u2n = M2E + tR * d2E;
       const C u3n = qM3[c] + tB * qd3[c];
       C s = K.alpha * pu[c];
-      s = s + (u1n - tL * pd2);
+      s = s + (u1n - tL * pd2[c]);
       s = s + (u2n - tR * pd1);
       s = s + (u3n - tB * pd4);
       // row L - 2 completes with its face j+1/2 (= L - 3/2)
       const C u4n = pM4 + tB * pd4;
       fin[c] = qP[c] + (u4n - tB * qd3[c]);
       if (row1 && lane_out) {
-        const long long o = (long long)(L - 1) * nx;
-        dst[o + (4 + c) * P] = (T)u1n;
-        dst[o + (8 + c) * P] = (T)u2n;
-        dst[o + (12 + c) * P] = (T)u3n;
+        const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
+        (dbase + (4 + c) * P)[o] = (T)u1n;
+        (dbase + (8 + c) * P)[o] = (T)u2n;
+        (dbase + (12 + c) * P)[o] = (T)u3n;
       }
       if (row2 && lane_out) {
-        const long long o = (long long)(L - 2) * nx;
-        dst[o + c * P] = (T)fin[c];
-        dst[o + (16 + c) * P] = (T)u4n;
+        const unsigned o = (unsigned)(L - 2) * unx + (unsigned)gi;
+        (dbase + c * P)[o] = (T)fin[c];
+        (dbase + (16 + c) * P)[o] = (T)u4n;
       }
       qP[c] = s;
       qM3[c] = pM3;
@@ -689,6 +774,9 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
     }
     pmu = mu1;
     pnu = nu1;
+    hpy = hy;
+    opr = orr;
+    opm = om;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       pu[c] = u[c];
@@ -698,12 +786,13 @@ __device__ __forceinline__ void march(const StepArgs& A, const Inst& in, Slots* 
       pdF[c] = dF[c];
       pusy[c] = usy[c];
       pdG[c] = dG[c];
+      hpu[c] = hu[c];
+      hpk[c] = hk[c];
 #pragma unroll
       for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
     }
   }
 
-  // ---- wave reductions and one atomic per strip
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
@@ -742,7 +831,7 @@ void step_kernel(StepArgs A) {
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
     if (LMP)
-      march<T, C, true>(A, in, A.slots + ii, xs, ys, lane);
+      march_lmp<T, C>(A, in, A.slots + ii, xs, ys, lane);
     else
       march_short<T, C>(A, in, A.slots + ii, xs, ys, lane);
   }
