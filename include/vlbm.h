@@ -172,6 +172,16 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
 lbm_status lbm_step_adjoint(lbm_ctx* ctx, const double* U_n_dev,
                             const double* Ubar_np1_dev, double* Ubar_n_dev);
 
+/* The same adjoint with theta^n supplied by the caller instead of recomputed:
+ * theta_x_dev / theta_y_dev are the face fields that lbm_step_theta wrote for
+ * the step from U_n (layouts as there), e.g. while a checkpointed segment is
+ * recomputed; a^n is a_fixed or follows lambda^n of U_n.  Same restrictions
+ * and aliasing rules as lbm_step_adjoint; Ubar_n must not alias the theta
+ * fields.  Asynchronous; does not change the context's state. */
+lbm_status lbm_step_adjoint_theta(lbm_ctx* ctx, const double* U_n_dev,
+                                  const double* theta_x_dev, const double* theta_y_dev,
+                                  const double* Ubar_np1_dev, double* Ubar_n_dev);
+
 /* Adjoint of the initialisation map u0 -> (u0, M_1..M_4(u0; a^0)) with a^0
  * held fixed: u0bar = Ubar0[u] + sum_k J_{M_k}(u0)^T Ubar0[u_k].
  * u0 and u0bar: float64 [4][ny][nx]; Ubar0: float64 state. */

@@ -8,9 +8,11 @@ values of the forward pass (a fixed active set; with a fixed kinetic speed
 and theta = 1 everywhere this is the exact derivative of the map).
 
 Memory: the forward pass keeps one state every `checkpoint_every` steps;
-the backward pass restores each checkpoint, recomputes its segment keeping
-the segment's states, and runs the adjoint kernel step by step in reverse
-(lbm_step_adjoint), then maps the result back through the initialisation
+the backward pass restores each checkpoint and recomputes its segment with
+lbm_step_theta, keeping each step's input state and face factors theta, then
+runs the adjoint kernel step by step in reverse with those factors
+(lbm_step_adjoint_theta; the same theta that lbm_step_adjoint would
+recompute), and finally maps the result back through the initialisation
 (lbm_init_adjoint).  All arithmetic runs in the HIP library.
 """
 from __future__ import annotations
@@ -53,14 +55,18 @@ class _Rollout(torch.autograd.Function):
         spare = torch.empty_like(ubar)
         for seg in range(len(ckpts) - 1, -1, -1):
             n = min(k, nsteps - seg * k)
-            # recompute the segment's states from its checkpoint
-            states = [ckpts[seg]]
+            # recompute the segment from its checkpoint: each step's input
+            # state and its face factors
             s.set_state(ckpts[seg])
-            for _ in range(n - 1):
-                s.step(1)
+            states, thetas = [], []
+            for _ in range(n):
                 states.append(s.get_state())
-            for st in reversed(states):
-                B.lbm_step_adjoint(s.ctx, st, ubar, spare)
+                tx = torch.empty((ny, nx + 1), dtype=torch.float64, device=u0.device)
+                ty = torch.empty((ny + 1, nx), dtype=torch.float64, device=u0.device)
+                B.lbm_step_theta(s.ctx, tx, ty)
+                thetas.append((tx, ty))
+            for st, (tx, ty) in zip(reversed(states), reversed(thetas)):
+                B.lbm_step_adjoint_theta(s.ctx, st, tx, ty, ubar, spare)
                 ubar, spare = spare, ubar
         u0bar = torch.empty_like(u0)
         B.lbm_init_adjoint(s.ctx, u0.contiguous(), ubar, u0bar)

@@ -37,7 +37,7 @@ EXPORTS = [
     "lbm_workspace_bytes", "lbm_batch_workspace_bytes", "lbm_init", "lbm_init_batch",
     "lbm_step", "lbm_step_graph", "lbm_step_theta", "lbm_moments", "lbm_diagnostics",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_adjoint",
-    "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
+    "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -101,6 +101,7 @@ def lib():
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp]
         L.lbm_step_adjoint.argtypes = [vp, vp, vp, vp]
+        L.lbm_step_adjoint_theta.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_init_adjoint.argtypes = [vp, vp, vp, vp]
         L.lbm_autotune.argtypes = [vp, ctypes.c_char_p]
         L.lbm_set_launch.argtypes = [vp, i32, i32]
@@ -292,6 +293,18 @@ def lbm_step_adjoint(ctx, U_n, Ubar_np1, Ubar_n):
     for t, name in ((U_n, "U_n"), (Ubar_np1, "Ubar_np1"), (Ubar_n, "Ubar_n")):
         _require_cuda(t, torch.float64, 20 * nx * ny, name)
     return _check(lib().lbm_step_adjoint(ctx, _ptr(U_n), _ptr(Ubar_np1), _ptr(Ubar_n)), ctx)
+
+
+def lbm_step_adjoint_theta(ctx, U_n, theta_x, theta_y, Ubar_np1, Ubar_n):
+    import torch
+
+    nx, ny = _inst_shape(ctx)
+    for t, name in ((U_n, "U_n"), (Ubar_np1, "Ubar_np1"), (Ubar_n, "Ubar_n")):
+        _require_cuda(t, torch.float64, 20 * nx * ny, name)
+    _require_cuda(theta_x, torch.float64, ny * (nx + 1), "theta_x")
+    _require_cuda(theta_y, torch.float64, (ny + 1) * nx, "theta_y")
+    return _check(lib().lbm_step_adjoint_theta(ctx, _ptr(U_n), _ptr(theta_x), _ptr(theta_y),
+                                               _ptr(Ubar_np1), _ptr(Ubar_n)), ctx)
 
 
 def lbm_init_adjoint(ctx, u0, Ubar0, u0bar):

@@ -677,8 +677,8 @@ void lbm_destroy(lbm_ctx* c) {
 }  // extern "C"
 
 // ------------------------------------------------------------- adjoint entry points
-extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double* Ub1,
-                                       double* Ub0) {
+namespace {
+lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const double* Ub0) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
@@ -689,6 +689,38 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())
     return fail(c, LBM_EINVAL, "U_n must not be one of the context's own state buffers");
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" lbm_status lbm_step_adjoint_theta(lbm_ctx* c, const double* U, const double* tx,
+                                             const double* ty, const double* Ub1, double* Ub0) {
+  lbm_status st = adjoint_checks(c, U, Ub1, Ub0);
+  if (st != LBM_OK) return st;
+  if (!tx || !ty) return fail(c, LBM_EINVAL, "theta buffers must be device pointers");
+  if ((const double*)Ub0 == tx || (const double*)Ub0 == ty)
+    return fail(c, LBM_EINVAL, "Ubar_n must not alias the theta fields");
+  // a^n: fixed, or from lambda^n of U_n in the slot the next forward step
+  // clears before it reads it (no other slot is touched)
+  const int scratch = (int)((c->step + 2) % 3);
+  hipError_t e = hipSuccess;
+  if (c->p.a_mode != LBM_A_FIXED) {
+    e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
+    if (e == hipSuccess)
+      e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, c->plane, U, c->slots, scratch,
+                                    LBM_FP64, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
+  }
+  e = vlbm::launch_adjoint_step(c->sc, c->insts[0], c->plane, U, Ub1, Ub0, tx, ty, c->slots,
+                                scratch, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double* Ub1,
+                                       double* Ub0) {
+  lbm_status st0 = adjoint_checks(c, U, Ub1, Ub0);
+  if (st0 != LBM_OK) return st0;
   const Inst& in = c->insts[0];
   double* tx = (double*)(c->ws + c->lay.theta);
   double* ty = tx + (size_t)(in.nx + 1) * in.ny;

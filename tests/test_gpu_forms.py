@@ -171,6 +171,38 @@ def test_step_adjoint_dot_product(gpu, lims):
     assert info.n_limited > 0
 
 
+@pytest.mark.parametrize("fixed_a", [False, True])
+@pytest.mark.parametrize("lims", [1 | 8, 1 | 2 | 8])
+def test_step_adjoint_theta_equals_recomputed(gpu, lims, fixed_a):
+    """lbm_step_adjoint_theta with the face factors lbm_step_theta wrote for
+    U_n gives the same Ubar_n, bit for bit, as lbm_step_adjoint, which
+    recomputes them (adaptive and fixed kinetic speed; limited faces present
+    in the LMP cases)."""
+    n = 64
+    u0 = cases.riemann4(n, seed=2)
+    kw = dict(limiters=lims, a_beta=1.1)
+    if fixed_a:
+        kw = dict(limiters=lims, a_mode=B.LBM_A_FIXED,
+                  a_fixed=6.0 * oracle.lam(oracle.Config(nx=n, ny=n), u0)[0])
+    s = solver(u0, **kw)
+    s.step(10)
+    U = s.get_state()
+    tx = gpu.empty((n, n + 1), dtype=gpu.float64, device="cuda")
+    ty = gpu.empty((n + 1, n), dtype=gpu.float64, device="cuda")
+    B.lbm_step_theta(s.ctx, tx, ty)
+    if lims & 2:  # the LMP bounds limit faces at every extremum
+        assert bool((tx < 1).any()) and bool((ty < 1).any())
+    w = gpu.from_numpy(np.random.default_rng(8).normal(size=(20, n, n))).cuda()
+    a = gpu.empty_like(w)
+    b = gpu.empty_like(w)
+    B.lbm_step_adjoint(s.ctx, U, w, a)
+    B.lbm_step_adjoint_theta(s.ctx, U, tx, ty, w, b)
+    assert gpu.equal(a, b)
+    with pytest.raises(B.LbmError):
+        B.lbm_step_adjoint_theta(s.ctx, U, tx, ty, w, w)
+    s.close()
+
+
 def test_init_adjoint_dot_product(gpu):
     n = 48
     u0 = cases.gaussian_bump(n, seed=0)
