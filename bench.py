@@ -18,9 +18,20 @@ so the algorithmic traffic is 160 B per cell-update (FP32 state) and 320 B
 HBM3E peak.  `traffic` comes from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 counters recorded under profiles/ (null if absent for this kernel build).
 
+Beside them: `fp32_error`, the relative L1 difference of the density between
+the two forms after the same steps (the FP64 form is bit-identical to the
+oracle), and `copy_reference`, the runtime's device-to-device copy bandwidth
+and torch's elementwise-kernel bandwidth on the same GPU, with each form's
+achieved bandwidth as a fraction of the faster one.
+
 cpu_baseline: the FP64 CPU oracle (OpenMP over rows, all host cores) timed on
 a bounded sample of the same workload: the blast on a 2048 x 2048 grid for
 80 steps (about 10-20 s of host time).
+
+Other workloads (`--workload`): `rarefaction` (near-vacuum double
+rarefaction 2048^2, FP64, PP + LMP + pressure, outflow), `batch` (256 uneven
+four-quadrant instances, FP32 state, hipGraph replay) and `adjoint` (gradient
+of a 200-step 512^2 rollout); each prints one JSON line of the same shape.
 """
 from __future__ import annotations
 
@@ -96,7 +107,9 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    st = s.moments(check=False)[1]
+    m, st = s.moments(check=False)
+    rho = m[0].clone()
+    del m
     d = s.diagnostics()
     s.close()
     del s
@@ -111,7 +124,39 @@ def time_form(form, u0t, n, steps, warmup, autotune):
         "diag": {"t": d["t"], "lambda": d["lam"], "n_bad": d["n_bad"], "n_guard": d["n_guard"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-    }
+    }, rho
+
+
+def device_copy_gbs(gib=4.0):
+    """Bandwidth (bytes read + written per second, best of three) of two
+    plain device copies of `gib` GiB: the runtime's device-to-device copy and
+    torch's vectorised elementwise kernel writing 2 x src.  Practical
+    references next to the nominal peak."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn in (("runtime_copy", lambda: dst.copy_(src)),
+                     ("elementwise", lambda: torch.mul(src, 2.0, out=dst))):
+        fn()
+        best = min(_timed(fn, 1) for _ in range(3))
+        out[name] = 2.0 * 4 * n / (best * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def traffic_for(key):
@@ -148,9 +193,70 @@ def cpu_baseline(n, steps):
     oracle.run(cfg, S, steps)
     dt = time.perf_counter() - t0
     return {"value": n * n * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "FP64 oracle on the blast workload at %dx%d for %d steps (%.1f s), "
                       "OpenMP over rows" % (n, n, steps, dt)}
+
+
+def _cpu_line(cell_updates, dt, sample):
+    import oracle
+
+    return {"value": cell_updates / dt / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu_model": cpu_model(), "sample": sample}
+
+
+def cpu_rarefaction(n=2048, steps=40):
+    """The FP64 oracle on the rarefaction workload (bounded sample)."""
+    import oracle
+    from paper_2411_15001_amd import cases
+
+    cfg = oracle.Config(nx=n, ny=n, limiters=oracle.RHO_PP | oracle.RHO_LMP | oracle.PRESSURE,
+                        bc_x=1, bc_y=1)
+    S, _ = oracle.init(cfg, cases.double_rarefaction(n, seed=0))
+    t0 = time.perf_counter()
+    oracle.run(cfg, S, steps)
+    dt = time.perf_counter() - t0
+    return _cpu_line(n * n * steps, dt, "FP64 oracle, rarefaction %dx%d, PP + LMP + pressure, %d steps "
+                                        "(%.1f s), OpenMP over rows" % (n, n, steps, dt))
+
+
+def cpu_batch(sides, u0s, steps=2):
+    """The FP64 oracle over every instance of the ensemble for a few steps."""
+    import oracle
+
+    dt = 0.0
+    for n, u0 in zip(sides, u0s):
+        cfg = oracle.Config(nx=n, ny=n, dx=1.0 / n, limiters=oracle.RHO_PP | oracle.PRESSURE,
+                            a_beta=1.1, bc_x=1, bc_y=1)
+        S, _ = oracle.init(cfg, u0)
+        t0 = time.perf_counter()
+        oracle.run(cfg, S, steps)
+        dt += time.perf_counter() - t0
+    cells = sum(x * x for x in sides)
+    return _cpu_line(cells * steps, dt, "FP64 oracle (FP64 state), all %d instances for %d steps each "
+                                        "(%.1f s), OpenMP over rows" % (len(sides), steps, dt))
+
+
+def cpu_adjoint(u0, a_fixed, steps=50):
+    """The oracle's forward rollout with its complex-step tangent (theta and a
+    frozen at the forward values) on the differentiation workload."""
+    import numpy as np
+
+    import oracle
+
+    n = u0.shape[1]
+    cfg = oracle.Config(nx=n, ny=n, limiters=oracle.RHO_PP | oracle.PRESSURE, a_mode=oracle.A_FIXED,
+                        a_fixed=a_fixed)
+    d = np.random.default_rng(100).normal(size=u0.shape)
+    t0 = time.perf_counter()
+    S, Sim = oracle.init_frozen_cs(cfg, u0, 1e-30 * d, a_fixed)
+    for _ in range(steps):
+        Sn, tx, ty, info = oracle.step(cfg, S)
+        _, Sim = oracle.step_frozen_cs(cfg, S, Sim, tx, ty, info.a)
+        S = Sn
+    dt = time.perf_counter() - t0
+    return _cpu_line(n * n * steps, dt, "oracle forward rollout + complex-step directional derivative "
+                                        "(one direction), %dx%d, %d steps (%.1f s)" % (n, n, steps, dt))
 
 
 def _timed(fn, steps):
@@ -207,7 +313,8 @@ def bench_rarefaction(a):
                        "a = 4 lambda, fp64 form", "grid": [n, n]},
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("rarefaction%d_fp64" % n)},
-          status=int(st), launch=list(B.lbm_get_launch(s.ctx)))
+          status=int(st), launch=list(B.lbm_get_launch(s.ctx)),
+          **({} if a.no_cpu else {"cpu_baseline": cpu_rarefaction(n)}))
     s.close()
 
 
@@ -224,9 +331,9 @@ def bench_batch(a):
     sides = cases.batch_sides(256, seed=0)
     u0s = cases.batch_riemann4(256, seed=0, sides=sides)
     cells = sum(x * x for x in sides)
-    bs = BatchSolver(u0s, precision=B.LBM_FP32_STATE, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE,
-                     a_beta=1.1, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
-    del u0s
+    kw = dict(precision=B.LBM_FP32_STATE, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE, a_beta=1.1,
+              bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
+    bs = BatchSolver(u0s, **kw)
     init = bs.get_state()
     if not a.no_autotune:
         bs.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
@@ -241,8 +348,23 @@ def bench_batch(a):
     torch.cuda.synchronize()
     ms = _timed(lambda: bs.step_graph(a.steps), a.steps)
     st = bs.moments(0, check=False)[1]
+    launch = B.lbm_get_launch(bs.ctx)
+    bs.close()
     avg = ms / a.steps
     ach = 160.0 * cells / (avg * 1e-3) / 1e9
+    # each size class alone (its own ensemble, same launch shape, 100 steps)
+    per_class = {}
+    for side in sorted(set(sides)):
+        idx = [i for i, x in enumerate(sides) if x == side]
+        cb = BatchSolver([u0s[i] for i in idx], **kw)
+        cb.set_launch(*launch)
+        cb.step(5)
+        cms = _timed(lambda: cb.step(100), 100) / 100
+        cb.close()
+        cc = len(idx) * side * side
+        per_class[str(side)] = {"instances": len(idx), "cells": cc, "ms_per_step": cms,
+                                "glups": cc / (cms * 1e-3) / 1e9,
+                                "frac": 160.0 * cc / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     _line(METRIC, cells / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.steps, avg,
           "f32 (theta solve and CFL reduce f64)",
           {"workload": "batch of 256 four-quadrant problems, sides 128k with k ~ U{1..8} (seed 0), "
@@ -250,8 +372,8 @@ def bench_batch(a):
            "instances": 256, "cells": cells},
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": None}, status=int(st),
-          launch=list(B.lbm_get_launch(bs.ctx)))
-    bs.close()
+          launch=list(launch), per_class=per_class,
+          **({} if a.no_cpu else {"cpu_baseline": cpu_batch(sides, u0s)}))
 
 
 def bench_adjoint(a):
@@ -271,7 +393,8 @@ def bench_adjoint(a):
     probe = Solver(u0)  # lambda^0 of the initial data, from the library
     lam0 = probe.diagnostics()["lam"]
     probe.close()
-    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=4.4 * lam0, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE)
+    a_fixed = 4.4 * lam0
+    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=a_fixed, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE)
     t = Solver(cases.gaussian_bump_target(n), **kw)
     t.step(steps)
     rho_tgt = t.moments()[0].clone()
@@ -290,12 +413,17 @@ def bench_adjoint(a):
     reps = 3
     ms = _timed(lambda: [once() for _ in range(reps)], reps) / reps
     cell_steps = n * n * steps
+    ach = (320.0 + 336.0 + 496.0) * cell_steps / (ms * 1e-3) / 1e9
     _line("cell-steps/s of a forward + adjoint rollout (GLUPS)", cell_steps / (ms * 1e-3) / 1e9,
           "GLUPS", steps, 0, ms / steps, "f64",
           {"workload": "gradient of the density misfit after 200 steps w.r.t. u0, 512x512 periodic "
                        "Gaussian bump, fixed a, checkpoints every 20", "grid": [n, n]},
-          {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-           "traffic": None}, ms_per_gradient=ms)
+          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": None}, ms_per_gradient=ms,
+          roofline_scope="whole gradient: algorithmic bytes of the forward (320 B), recompute "
+                         "(336 B: state + theta) and adjoint (496 B: U, Ubar in, theta, Ubar out) "
+                         "cell-steps over the gradient time; state copies excluded",
+          **({} if a.no_cpu else {"cpu_baseline": cpu_adjoint(u0, a_fixed)}))
 
 
 def main():
@@ -318,8 +446,9 @@ def main():
     u0t = torch.from_numpy(u0).cuda()
     del u0
     forms = {}
+    rho = {}
     for form in a.forms.split(","):
-        forms[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
+        forms[form], rho[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
         forms[form]["roofline"]["traffic"] = traffic_for("blast%d_%s" % (a.n, form))
         print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
             form, forms[form]["value"], forms[form]["ms_per_step"],
@@ -348,6 +477,19 @@ def main():
     }
     if "fp32" in forms and "fp64" in forms:
         out["fp32_speedup_over_fp64"] = forms["fp32"]["value"] / forms["fp64"]["value"]
+        # both forms ran warmup + steps steps from the same initial state; the
+        # FP64 form is bit-identical to the oracle (parity tests), so it stands
+        # in for the oracle at this size
+        err = float((rho["fp32"] - rho["fp64"]).abs().sum() / rho["fp64"].abs().sum())
+        out["fp32_error"] = {"rel_l1_rho_vs_fp64": err, "steps": a.warmup + a.steps,
+                             "grid": [a.n, a.n]}
+    del rho
+    torch.cuda.empty_cache()
+    cg = device_copy_gbs()
+    best = max(cg.values())
+    out["copy_reference"] = {"gbs": best, "kind": "fastest of %s, 4 GiB, best of 3" % sorted(cg),
+                             "measured": cg,
+                             "frac": {k: v["roofline"]["achieved"] / best for k, v in forms.items()}}
     if a.calib_gib > 0:
         out["calibration_copy"] = calibration_copy(a.calib_gib)
     if not a.no_cpu:

@@ -148,14 +148,22 @@ def test_table1_on_gpu():
         s.close()
 
 
-def test_c1_full_size():
+def test_c1_full_size(tmp_path):
     """2048^2 near-vacuum double rarefaction, PP + LMP + pressure, a = 4
-    lambda^n, outflow, in the benchmark's launch shape: the first steps equal
-    the oracle bit for bit at full size, and 1000 steps stay admissible."""
+    lambda^n, outflow, in the benchmark's launch shape (from a copy of the
+    committed autotune cache): the first steps equal the oracle bit for bit at
+    full size, and 1000 steps stay admissible."""
+    import os
+    import shutil
+
+    cache = str(tmp_path / "autotune_cache.json")
+    shutil.copy(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "paper_2411_15001_amd", "autotune_cache.json"), cache)
     n = 2048
     u0 = cases.double_rarefaction(n, seed=0)
     ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, bc_x=1, bc_y=1)
     s = Solver(u0, **okw(ocfg))
+    s.autotune(cache)
     s.step(2)
     G = s.get_state().cpu().numpy()
     S, _ = oracle.init(ocfg, u0)
