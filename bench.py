@@ -352,17 +352,18 @@ def bench_batch(a):
     bs.close()
     avg = ms / a.steps
     ach = 160.0 * cells / (avg * 1e-3) / 1e9
-    # each size class alone (its own ensemble, same launch shape, 100 steps)
+    # each size class alone (its own ensemble with its default launch shape,
+    # 100 steps)
     per_class = {}
     for side in sorted(set(sides)):
         idx = [i for i, x in enumerate(sides) if x == side]
         cb = BatchSolver([u0s[i] for i in idx], **kw)
-        cb.set_launch(*launch)
         cb.step(5)
         cms = _timed(lambda: cb.step(100), 100) / 100
+        cl = list(B.lbm_get_launch(cb.ctx))
         cb.close()
         cc = len(idx) * side * side
-        per_class[str(side)] = {"instances": len(idx), "cells": cc, "ms_per_step": cms,
+        per_class[str(side)] = {"instances": len(idx), "cells": cc, "ms_per_step": cms, "launch": cl,
                                 "glups": cc / (cms * 1e-3) / 1e9,
                                 "frac": 160.0 * cc / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     _line(METRIC, cells / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.steps, avg,
