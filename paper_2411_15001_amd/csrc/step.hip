@@ -581,6 +581,32 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
 
   double lmax = 0.0;
   unsigned n_bad = 0, n_guard = 0, n_lim = 0;
+  // float64 state: the stores of a row are issued at the top of the next
+  // iteration, right after its prefetch, so that they complete under that
+  // iteration's compute rather than ahead of its wait for the prefetched
+  // row (measured 3% faster on the 2048^2 rarefaction; with the float32
+  // state, and in the short march, the plain order measured faster)
+  constexpr bool kDefer = sizeof(T) == 8;
+  T sv[20];
+  unsigned so1 = 0, so2 = 0;
+  bool sw1 = false, sw2 = false;
+  auto flush = [&]() {
+    if (sw1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        put(&(dbase + (4 + c) * P)[so1], sv[c]);
+        put(&(dbase + (8 + c) * P)[so1], sv[4 + c]);
+        put(&(dbase + (12 + c) * P)[so1], sv[8 + c]);
+      }
+    }
+    if (sw2) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        put(&(dbase + c * P)[so2], sv[12 + c]);
+        put(&(dbase + (16 + c) * P)[so2], sv[16 + c]);
+      }
+    }
+  };
 
   T raw[20], hraw[8] = {}, oraw[2] = {};
   {
@@ -629,6 +655,10 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
         oraw[0] = sbase[oo];
         oraw[1] = (sbase + P)[oo];
       }
+    }
+    if constexpr (kDefer) {
+      flush();
+      __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- row L: fluxes, the x-face i+1/2 and the y-face L - 1/2
@@ -760,20 +790,34 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       // row L - 2 completes with its face j+1/2 (= L - 3/2)
       const C u4n = pM4 + tB * pd4;
       fin[c] = qP[c] + (u4n - tB * qd3[c]);
-      if (row1 && lane_out) {
-        const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
-        put(&(dbase + (4 + c) * P)[o], (T)u1n);
-        put(&(dbase + (8 + c) * P)[o], (T)u2n);
-        put(&(dbase + (12 + c) * P)[o], (T)u3n);
-      }
-      if (row2 && lane_out) {
-        const unsigned o = (unsigned)(L - 2) * unx + (unsigned)gi;
-        put(&(dbase + c * P)[o], (T)fin[c]);
-        put(&(dbase + (16 + c) * P)[o], (T)u4n);
+      if constexpr (kDefer) {
+        sv[c] = (T)u1n;
+        sv[4 + c] = (T)u2n;
+        sv[8 + c] = (T)u3n;
+        sv[12 + c] = (T)fin[c];
+        sv[16 + c] = (T)u4n;
+      } else {
+        if (row1 && lane_out) {
+          const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
+          put(&(dbase + (4 + c) * P)[o], (T)u1n);
+          put(&(dbase + (8 + c) * P)[o], (T)u2n);
+          put(&(dbase + (12 + c) * P)[o], (T)u3n);
+        }
+        if (row2 && lane_out) {
+          const unsigned o = (unsigned)(L - 2) * unx + (unsigned)gi;
+          put(&(dbase + c * P)[o], (T)fin[c]);
+          put(&(dbase + (16 + c) * P)[o], (T)u4n);
+        }
       }
       qP[c] = s;
       qM3[c] = pM3;
       qd3[c] = pM3 - puk[2][c];
+    }
+    if constexpr (kDefer) {
+      sw1 = row1 && lane_out;
+      so1 = (unsigned)(L - 1) * unx + (unsigned)gi;
+      sw2 = row2 && lane_out;
+      so2 = (unsigned)(L - 2) * unx + (unsigned)gi;
     }
     if (row2 && lane_out) {
       // wavespeed of the stored new state, in float64
@@ -804,6 +848,8 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
     }
   }
+
+  if constexpr (kDefer) flush();
 
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {

@@ -231,6 +231,35 @@ def test_fp32_form_against_oracle():
     s32.close()
 
 
+def test_fp32_form_1024_against_oracle():
+    """FP32-state form on the blast at 1024^2 (the accuracy size of the
+    8192^2 benchmark), 500 steps, against the FP64 oracle: relative L1 error
+    of the density within the 1e-4 target or, where the PP-limited blast
+    has become sensitive, within three times the oracle's own spread from a
+    one-float32-rounding perturbation of the initial data (+1e-4).  Both
+    numbers are printed."""
+    n, steps = 1024, 500
+    u0 = cases.blast(n, seed=0)
+    ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8)
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, steps)
+    rng = np.random.default_rng(1)
+    Sp, _ = oracle.init(ocfg, u0 * (1 + 6e-8 * rng.uniform(-1, 1, u0.shape)))
+    Sp, _, _, _ = oracle.run(ocfg, Sp, steps)
+
+    def l1(a, b):
+        return np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum()
+
+    floor = l1(Sp, S)
+    s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
+    s32.step(steps)
+    e = l1(s32.moments().cpu().numpy(), S)
+    print("fp32 blast 1024^2 rel L1 rho after %d steps %.3e (oracle floor %.3e)" % (steps, e, floor))
+    assert s32.diagnostics()["n_bad"] == 0
+    assert e <= max(1e-4, 3 * floor + 1e-4)
+    s32.close()
+
+
 def test_graph_replay_equals_eager(gpu):
     """lbm_step_graph replays (with eager work and syncs between them) give the
     same states as eager launches, for every slot phase."""
