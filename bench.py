@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--workload", default="blast", choices=["blast", "rarefaction", "batch", "adjoint"],
                     help="blast: the headline 8192^2 line; the others time the LMP, batching and "
                          "differentiation forms on their own workloads")
+    ap.add_argument("--no-per-class", action="store_true",
+                    help="batch workload: skip the per-size-class timings")
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -355,7 +357,7 @@ def bench_batch(a):
     # each size class alone (its own ensemble with its default launch shape,
     # 100 steps)
     per_class = {}
-    for side in sorted(set(sides)):
+    for side in ([] if a.no_per_class else sorted(set(sides))):
         idx = [i for i, x in enumerate(sides) if x == side]
         cb = BatchSolver([u0s[i] for i in idx], **kw)
         cb.step(5)
