@@ -138,7 +138,9 @@ def make_params(nx, ny, dx=None, gamma=1.4, alpha=0.5, order=2,
                 a_fixed=0.0, bc_x=LBM_BC_PERIODIC, bc_y=LBM_BC_PERIODIC, sponge=0,
                 precision=LBM_FP64, eps=1e-16, rlmp_lo=0.999, rlmp_hi=1.001,
                 theta_margin=0.0, unsafe=0):
-    return lbm_params(nx, ny, 1.0 / nx if dx is None else dx, gamma, alpha, order, limiters,
+    if dx is None:
+        dx = 1.0 / nx if nx > 0 else 1.0  # nx < 1 is refused by the library
+    return lbm_params(nx, ny, dx, gamma, alpha, order, limiters,
                       a_mode, a_beta, a_fixed, bc_x, bc_y, sponge, precision, eps, rlmp_lo,
                       rlmp_hi, theta_margin, unsafe)
 

@@ -31,9 +31,19 @@ long long strips_x(int nx) { return (nx + 63) / 64; }
 
 long long strips_y(int ny, int h) { return (ny + h - 1) / h; }
 
+// Grid sizes the kernels address: cells of one instance are indexed with
+// 32-bit row * nx + column offsets, and the edge lanes step two columns past
+// a strip, so each side stays within 2^30 and an instance below 2^32 cells.
+const char* check_shape(int32_t nx, int32_t ny) {
+  if (nx < 1 || ny < 1) return "nx and ny must be >= 1";
+  if (nx > (1 << 30) || ny > (1 << 30)) return "nx and ny must be <= 2^30";
+  if ((long long)nx * ny > 0xFFFFFFFFll) return "an instance must have fewer than 2^32 cells";
+  return nullptr;
+}
+
 const char* check_params(const lbm_params* p) {
   if (!p) return "params is NULL";
-  if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+  if (const char* m = check_shape(p->nx, p->ny)) return m;
   if (!(p->dx > 0.0) || !isfinite(p->dx)) return "dx must be > 0";
   if (!(p->gamma > 1.0)) return "gamma must be > 1";
   if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return "alpha must lie in [0, 1)";
@@ -269,7 +279,7 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   if (const char* m = check_params(p)) return fail(nullptr, LBM_EINVAL, m);
   if (n < 1 || !nx || !ny) return fail(nullptr, LBM_EINVAL, "need at least one instance");
   for (int i = 0; i < n; ++i)
-    if (nx[i] < 1 || ny[i] < 1) return fail(nullptr, LBM_EINVAL, "instance sizes must be >= 1");
+    if (const char* m = check_shape(nx[i], ny[i])) return fail(nullptr, LBM_EINVAL, m);
   if (!u0 || !ws) return fail(nullptr, LBM_EINVAL, "u0 and workspace must be device pointers");
   if (((uintptr_t)ws) % kAlign) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
   if (p->sponge > 0 && n > 1) return fail(nullptr, LBM_ENOTSUP, "sponge layers are single-instance only");
@@ -356,7 +366,7 @@ size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n, const int32_t* 
                                  const int32_t* ny) {
   if (check_params(p) || n < 1 || !nx || !ny) return 0;
   for (int i = 0; i < n; ++i)
-    if (nx[i] < 1 || ny[i] < 1) return 0;
+    if (check_shape(nx[i], ny[i])) return 0;
   return layout(p, n, nx, ny).total;
 }
 
@@ -689,6 +699,7 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())
     return fail(c, LBM_EINVAL, "U_n must not be one of the context's own state buffers");
+  if (c->insts[0].ny > 65535) return fail(c, LBM_ENOTSUP, "the adjoint supports ny <= 65535");
   return LBM_OK;
 }
 }  // namespace
