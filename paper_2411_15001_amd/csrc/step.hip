@@ -44,34 +44,11 @@ __device__ __forceinline__ X vmin(X a, X b) { return (b < a) ? b : a; }
 template <class X>
 __device__ __forceinline__ X vmax(X a, X b) { return (b > a) ? b : a; }
 
-// Value held by lane - 1 / lane + 1 (own value at the wave ends): DPP
-// whole-wave shifts (wave_shr:1 = 0x138, wave_shl:1 = 0x130), one VALU move
-// per dword and no LDS traffic.
-__device__ __forceinline__ int dpp_left(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
-}
-__device__ __forceinline__ int dpp_right(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
-}
-__device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(dpp_left(__float_as_int(v)));
-}
-__device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(dpp_right(__float_as_int(v)));
-}
-__device__ __forceinline__ double from_left(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_left((int)(b & 0xffffffffll)), hi = dpp_left((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double from_right(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_right((int)(b & 0xffffffffll)), hi = dpp_right((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-// As above, but the lane without a source (63 for from_right_or, 0 for
-// from_left_or) receives `edge` instead of its own value: the DPP move leaves
-// that lane's destination untouched, and the destination starts as `edge`.
+// Value held by lane - 1 / lane + 1 through DPP whole-wave shifts
+// (wave_shr:1 = 0x138, wave_shl:1 = 0x130): one VALU move per dword, no LDS
+// traffic.  The lane without a source (63 for from_right_or, 0 for
+// from_left_or) receives `edge`: the DPP move leaves that lane's destination
+// untouched, and the destination starts as `edge`.
 __device__ __forceinline__ int dpp_right_or(int v, int e) {
   return __builtin_amdgcn_update_dpp(e, v, 0x130, 0xf, 0xf, false);
 }
@@ -134,22 +111,6 @@ __device__ __forceinline__ double theta_rho_lmp(double rs, double D, double kapp
   return num <= D ? 1.0 : num / D;
 }
 
-// Section 3.4: kappa over the spectral radius of B^{-1/2} A B^{-1/2}
-__device__ __forceinline__ double theta_p(double r0, double m1, double m2, double E, double Dr,
-                                          double Dm1, double Dm2, double DE, double kappa,
-                                          double eps) {
-  const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
-  const double g1 = 2.0 * (Dr * E + DE * r0 - Dm1 * m1 - Dm2 * m2);
-  const double g2 = Dm1 * Dm1 + Dm2 * Dm2 - 2.0 * Dr * DE;
-  double disc = g1 * g1 - 4.0 * g0 * g2;
-  disc = vmax(0.0, disc);
-  const double e1 = fabs(Dr) / r0;
-  const double e2 = (fabs(g1) + sqrt(disc)) / (-2.0 * g0);
-  const double r = vmax(e1, e2);
-  if (r == 0.0) return kHuge;
-  return vmax(0.0, kappa / r - eps);
-}
-
 // Margin of the division-free test below: c = 1 + 2^-30.
 constexpr double kFastMargin = 1.0 + 0x1p-30;
 
@@ -197,7 +158,8 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
     const double Dn = -2.0 * g0;
     const bool fast_p = fast_rho && N * kFastMargin <= kappa * Dn;
     if (!fast_p) {
-      // the expressions of theta_p, reusing g0, g1, disc, N and -2 g0
+      // theta^p = max(0, kappa / r - eps) with r the larger of |D| / rho* and
+      // (|g1| + sqrt(disc)) / (-2 g0) (Section 3.4), reusing g0, g1, disc, N
       const double e1 = fabs(D) / r0;
       const double e2 = N / Dn;
       const double r = vmax(e1, e2);
