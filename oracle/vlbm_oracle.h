@@ -14,6 +14,14 @@
  * Face arrays: theta_x[ny][nx+1], entry (j, i) is the blending factor of the
  * x-face between cells (i-1, j) and (i, j); theta_y[ny+1][nx], entry (j, i) is
  * the factor of the y-face between cells (i, j-1) and (i, j).
+ *
+ * Parity unpinned (conventions the paper leaves open; the readings are fixed
+ * here but no value printed in the paper or fixed by mathematics checks them):
+ * the two zero-gradient ghost layers of outflow boundaries (bc_x / bc_y = 1;
+ * only the convergence of Sod data to the exact Riemann solution checks them
+ * indirectly), the sponge layer (sponge > 0), the event counters of orc_info
+ * (n_guard, n_limited, n_bad), and evaluating M_k with the current a^n without
+ * rescaling the distributions when a changes between steps.
  */
 #ifndef VLBM_ORACLE_H
 #define VLBM_ORACLE_H
