@@ -135,8 +135,12 @@ lbm_status lbm_init_batch(const lbm_params* p, int32_t n, const int32_t* nx,
  * kernel launch each, asynchronous, no host synchronisation. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
-/* Same steps, replayed from a hipGraph that holds nsteps launches (captured
- * on first use for each (nsteps, phase) and cached in the context). */
+/* Same steps, replayed from a hipGraph of the launches (captured on first use
+ * for each (length, phase) and cached in the context, at most 32 graphs).  A
+ * graph holds at most 1020 launches; longer runs replay it (1020 is a
+ * multiple of the 6-step phase period, so one graph serves every chunk).  The
+ * first call for a new length synchronises with the capture; later calls are
+ * asynchronous. */
 lbm_status lbm_step_graph(lbm_ctx* ctx, int32_t nsteps);
 
 /* One step that also writes the face factors: theta_x_dev float64

@@ -392,13 +392,23 @@ lbm_status lbm_step(lbm_ctx* c, int32_t nsteps) {
   return LBM_OK;
 }
 
-lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
-  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
-  if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
-  if (nsteps == 0) return LBM_OK;
+}  // extern "C"
+
+namespace {
+// A graph holds at most kGraphChunk launches; longer runs replay it.  The
+// chunk is a multiple of 6, the period of the (lambda slot, buffer) phase, so
+// one graph serves every chunk of a run.  At most kMaxGraphs graphs are kept.
+constexpr int32_t kGraphChunk = 1020;
+constexpr size_t kMaxGraphs = 32;
+
+lbm_status replay_graph(lbm_ctx* c, int32_t nsteps) {
   const auto key = std::make_tuple((int)nsteps, (int)(c->step % 3), (int)(c->step & 1));
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
+    if (c->graphs.size() >= kMaxGraphs) {
+      for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+      c->graphs.clear();
+    }
     // record on a private stream (the legacy default stream cannot be
     // captured); the graph is then launched on the context's stream
     hipError_t e = hipSuccess;
@@ -415,7 +425,10 @@ lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
     c->step = step0;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->cap_stream, &g);
-    if (st != LBM_OK) return st;
+    if (st != LBM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
@@ -426,6 +439,21 @@ lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
   hipError_t e = hipGraphLaunch(it->second, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
   c->step += nsteps;
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+  while (nsteps > 0) {
+    const int32_t k = nsteps > kGraphChunk ? kGraphChunk : nsteps;
+    const lbm_status st = replay_graph(c, k);
+    if (st != LBM_OK) return st;
+    nsteps -= k;
+  }
   return LBM_OK;
 }
 

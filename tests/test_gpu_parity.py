@@ -283,6 +283,22 @@ def test_graph_replay_equals_eager(gpu):
     b.close()
 
 
+def test_graph_replay_long_runs_in_chunks(gpu):
+    """A graph replay longer than one graph (2 x 1020 + 7 steps, replayed in
+    chunks of 1020 launches) equals eager stepping bit for bit."""
+    n = 64
+    u0 = cases.riemann4(n, seed=4)
+    kw = dict(limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+    a = Solver(u0, **kw)
+    b = Solver(u0, **kw)
+    a.step_graph(2 * 1020 + 7)
+    b.step(2 * 1020 + 7)
+    assert gpu.equal(a.get_state(), b.get_state())
+    assert a.diagnostics()["step"] == b.diagnostics()["step"] == 2 * 1020 + 7
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("lims", [1 | 8, 2 | 8])
 def test_determinism(lims):
     """The state after 40 steps does not depend on the launch shape (strip
