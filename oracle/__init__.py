@@ -74,6 +74,7 @@ class Info(ctypes.Structure):
         ("kappa", ctypes.c_double), ("lambda_new", ctypes.c_double),
         ("n_guard", ctypes.c_int64), ("n_limited", ctypes.c_int64),
         ("n_bad", ctypes.c_int64), ("bouchut", ctypes.c_int32),
+        ("n_lmp", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -217,12 +218,12 @@ def step(cfg: Config, S):
 
 
 def run(cfg: Config, S, nsteps, t=0.0):
-    """nsteps steps; returns (S_new, t_new, last_info, totals[guard, limited, bad])."""
+    """nsteps steps; returns (S_new, t_new, last_info, totals[guard, limited, bad, lmp])."""
     S = np.array(S, dtype=np.float64, order="C", copy=True)
     work = np.empty_like(S)
     tt = ctypes.c_double(t)
     info = Info()
-    totals = (ctypes.c_int64 * 3)(0, 0, 0)
+    totals = (ctypes.c_int64 * 4)(0, 0, 0, 0)
     P = cfg.params()
     rc = lib().orc_run(ctypes.byref(P), _p(S), _p(work), int(nsteps), ctypes.byref(tt),
                        ctypes.byref(info), totals)

@@ -350,6 +350,19 @@ int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x
   /* S7: collide and stream. */
   update_grid_d(P, T, gw, tx, ty, Snew);
 
+  /* LMP check: the new density of every cell against its eq. (29) bounds. */
+  int64_t n_lmp = 0;
+  if (P->order == 2 && (P->limiters & (ORC_RHO_LMP | ORC_RHO_RLMP))) {
+#pragma omp parallel for schedule(static) reduction(+ : n_lmp)
+    for (int j = 0; j < ny; ++j) {
+      for (int i = 0; i < nx; ++i) {
+        const size_t p = (size_t)(j + gw) * pw + (size_t)(i + gw);
+        const double r = Snew[(size_t)j * nx + i];
+        n_lmp += (r < mu[p] - ORC_LMP_TOL * fabs(mu[p])) || (r > nu[p] + ORC_LMP_TOL * fabs(nu[p]));
+      }
+    }
+  }
+
   /* S8: diagnostics of the new state. */
   int64_t bad1 = 0;
   const double lam1 = orc_lambda(P, Snew, &bad1);
@@ -363,6 +376,7 @@ int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x
     info->n_limited = n_limited;
     info->n_bad = bad1;
     info->bouchut = (a < 2.0 * lam / (1.0 - P->alpha)) ? 1 : 0;
+    info->n_lmp = n_lmp;
   }
   free(T);
   free(FX);
@@ -375,9 +389,9 @@ int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x
 }
 
 /* nsteps steps in place (S <- S^{n+nsteps}); work holds one more state.
- * totals accumulates (n_guard, n_limited, n_bad) over the steps. */
+ * totals accumulates (n_guard, n_limited, n_bad, n_lmp) over the steps. */
 int orc_run(const orc_params* P, double* S, double* work, int32_t nsteps,
-            double* t, orc_info* last, int64_t totals[3]) {
+            double* t, orc_info* last, int64_t totals[4]) {
   const size_t n = (size_t)20 * (size_t)P->nx * (size_t)P->ny;
   orc_info info;
   memset(&info, 0, sizeof(info));
@@ -390,6 +404,7 @@ int orc_run(const orc_params* P, double* S, double* work, int32_t nsteps,
       totals[0] += info.n_guard;
       totals[1] += info.n_limited;
       totals[2] += info.n_bad;
+      totals[3] += info.n_lmp;
     }
   }
   if (last) *last = info;

@@ -60,7 +60,14 @@ typedef struct {
   int64_t n_limited; /* faces with theta < 1 (left and bottom faces of every cell) */
   int64_t n_bad;     /* output cells with rho <= 0, p <= 0 or non-finite wavespeed */
   int32_t bouchut;   /* 1 if a < 2 lambda / (1 - alpha) */
+  int64_t n_lmp;     /* with LMP or RLMP limiting: output cells whose new density
+                        leaves the eq. (29) bounds [mu, nu] of the cell by more
+                        than ORC_LMP_TOL relative (the convex decomposition of
+                        eq. (28) keeps it inside under LMP) */
 } orc_info;
+
+/* Relative slack of the LMP check above: rounding of the update only. */
+#define ORC_LMP_TOL 1e-12
 
 #ifdef __cplusplus
 extern "C" {
@@ -87,7 +94,7 @@ int orc_init(const orc_params* P, const double* u0, double* S, orc_info* info);
 int orc_step(const orc_params* P, const double* S, double* Snew,
              double* theta_x, double* theta_y, orc_info* info);
 int orc_run(const orc_params* P, double* S, double* work, int32_t nsteps,
-            double* t, orc_info* last, int64_t totals[3]);
+            double* t, orc_info* last, int64_t totals[4]);
 
 /* The step map with theta and a given (frozen). */
 int orc_step_frozen(const orc_params* P, const double* S, const double* theta_x,

@@ -571,3 +571,23 @@ def test_complex_step_tangent_matches_finite_differences(orc):
     S0p, _ = orc.init(cfg, u0 + eps * w)
     S0m, _ = orc.init(cfg, u0 - eps * w)
     assert np.abs(Sim / h - (S0p - S0m) / (2 * eps)).max() <= 1e-7 * np.abs(Sim / h).max()
+
+
+def test_lmp_check_counter(orc):
+    """The oracle's LMP check (new density of every cell against its eq. (29)
+    bounds): zero under the LMP limiter, with or without PP, on four-quadrant,
+    Lax-Liu and near-vacuum data -- the convex decomposition of eq. (28) with
+    every limited face state inside [mu, nu] keeps the update inside; and
+    positive under RLMP alone (negative control: its bounds are relaxed by
+    0.1%, Section 3.3.4, so the update may leave the strict ones)."""
+    n = 64
+    for u0 in (cases.riemann4(n, seed=3), cases.lax_liu3(n), cases.double_rarefaction(n)):
+        for lims, expect_zero in ((1 | 2 | 8, True), (2 | 8, True), (4 | 8, False)):
+            cfg = orc.Config(nx=n, ny=n, limiters=lims, bc_x=1, bc_y=1)
+            S, _ = orc.init(cfg, u0)
+            S, _, _, tot = orc.run(cfg, S, 50)
+            assert (tot[3] == 0) == expect_zero, (lims, tot)
+    # without density bounds in the limiter set there is nothing to check
+    cfg = orc.Config(nx=n, ny=n, limiters=1 | 8, bc_x=1, bc_y=1)
+    S, _ = orc.init(cfg, cases.riemann4(n, seed=3))
+    assert orc.run(cfg, S, 10)[3][3] == 0
