@@ -18,6 +18,10 @@ so the algorithmic traffic is 160 B per cell-update (FP32 state) and 320 B
 HBM3E peak.  `traffic` comes from the rocprofv3 FETCH_SIZE / WRITE_SIZE
 counters recorded under profiles/ (null if absent for this kernel build).
 
+Each form also reports `conservation_drift`: the largest change of the
+totals of rho, m1, m2 and E (compensated device sums) over its warm-up and
+timed steps, relative to mass + energy (periodic grid: conserved).
+
 Beside them: `fp32_error`, the relative L1 difference of the density between
 the two forms after the same steps (the FP64 form is bit-identical to the
 oracle), and `copy_reference`, the runtime's device-to-device copy bandwidth
@@ -97,6 +101,7 @@ def time_form(form, u0t, n, steps, warmup, autotune):
         rows, waves = s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
     else:
         rows, waves = B.lbm_get_launch(s.ctx)
+    tot0 = s.totals()
     s.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -109,6 +114,8 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    tot1 = s.totals()
+    drift = max(abs(b - a) for a, b in zip(tot0, tot1)) / (abs(tot0[0]) + abs(tot0[3]))
     m, st = s.moments(check=False)
     rho = m[0].clone()
     del m
@@ -124,6 +131,7 @@ def time_form(form, u0t, n, steps, warmup, autotune):
         "value": glups, "ms_per_step": avg_ms, "wall_s": wall, "status": int(st),
         "launch": {"strip_rows": rows, "waves_per_group": waves},
         "diag": {"t": d["t"], "lambda": d["lam"], "n_bad": d["n_bad"], "n_guard": d["n_guard"]},
+        "conservation_drift": drift,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }, rho

@@ -104,6 +104,12 @@ typedef struct {
   int64_t n_limited;   /* faces with theta < 1 (left and bottom face of every cell) */
   int64_t n_bad;       /* cells with rho <= 0, p <= 0 or a non-finite wavespeed */
   int32_t bouchut;     /* a fixed a fell below 2 lambda / (1 - alpha) */
+  int64_t n_lmp;       /* with LMP or RLMP limiting (order 2): cells whose new
+                          density left the eq. (29) bounds [mu, nu] of the cell
+                          by more than the update's rounding (1e-12 relative in
+                          float64, 2e-6 with the float32 state).  Zero under LMP
+                          (eq. (28)); RLMP relaxes the bounds, so it may count
+                          there.  A check, not an error: no call fails on it. */
 } lbm_diag;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -154,6 +160,15 @@ lbm_status lbm_step_theta(lbm_ctx* ctx, double* theta_x_dev, double* theta_y_dev
  * since the last synchronising call (LBM_EPOSITIVITY, LBM_EGUARD,
  * LBM_EBOUCHUT) or LBM_OK, and clears the counters. */
 lbm_status lbm_moments(lbm_ctx* ctx, int32_t inst, double* u_out_dev);
+
+/* Totals of the conserved moments of instance `inst` over its cells:
+ * totals_host[0..3] = sum of rho, m1, m2, E of the moment slot (multiply by
+ * dx^2 for the integrals), by compensated (double-double) summation, so the
+ * result is within a few roundings of the exact sum of the stored values.
+ * On periodic grids the scheme conserves them (Section 1), so two calls
+ * bracket the conservation error of the steps between them.  totals_host is
+ * host memory for 4 doubles.  Synchronises; clears no counter. */
+lbm_status lbm_totals(lbm_ctx* ctx, int32_t inst, double* totals_host);
 
 /* Diagnostics of instance `inst`; synchronises; does not clear counters. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t inst, lbm_diag* out);

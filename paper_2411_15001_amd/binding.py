@@ -36,6 +36,7 @@ LBM_FP32_STATE = 1
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_batch_workspace_bytes", "lbm_init", "lbm_init_batch",
     "lbm_step", "lbm_step_graph", "lbm_step_theta", "lbm_moments", "lbm_diagnostics",
+    "lbm_totals",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_adjoint",
     "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
@@ -62,7 +63,7 @@ class lbm_diag(ctypes.Structure):
         ("lam", ctypes.c_double), ("a", ctypes.c_double), ("t", ctypes.c_double),
         ("step", ctypes.c_int64), ("n_guard", ctypes.c_int64),
         ("n_limited", ctypes.c_int64), ("n_bad", ctypes.c_int64),
-        ("bouchut", ctypes.c_int32),
+        ("bouchut", ctypes.c_int32), ("n_lmp", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -96,6 +97,7 @@ def lib():
         L.lbm_step_theta.argtypes = [vp, vp, vp]
         L.lbm_moments.argtypes = [vp, i32, vp]
         L.lbm_diagnostics.argtypes = [vp, i32, ctypes.POINTER(lbm_diag)]
+        L.lbm_totals.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.lbm_state_bytes.argtypes = [vp]
         L.lbm_state_bytes.restype = ctypes.c_size_t
         L.lbm_get_state.argtypes = [vp, vp]
@@ -262,6 +264,14 @@ def lbm_diagnostics(ctx, inst=0):
     d = lbm_diag()
     _check(lib().lbm_diagnostics(ctx, int(inst), ctypes.byref(d)), ctx)
     return d
+
+
+def lbm_totals(ctx, inst=0):
+    """(sum rho, sum m1, sum m2, sum E) of instance inst, compensated sums."""
+    _inst_shape(ctx, int(inst))
+    out = (ctypes.c_double * 4)()
+    _check(lib().lbm_totals(ctx, int(inst), out), ctx)
+    return tuple(out)
 
 
 def lbm_state_bytes(ctx):

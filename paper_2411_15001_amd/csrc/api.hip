@@ -18,6 +18,7 @@ using vlbm::Slots;
 namespace {
 
 constexpr int kMinStripRows = 4;  // bounds the work-item table in the workspace
+constexpr int kTotalsBlocks = 1024;  // workgroups of the totals reduction
 constexpr int kMaxStripRows = 4096;
 constexpr size_t kAlign = 256;
 
@@ -87,7 +88,7 @@ Scheme make_scheme(const lbm_params* p) {
 }
 
 struct Layout {
-  size_t slots, slots_save, insts, items, bufA, bufB, theta, total;
+  size_t slots, slots_save, red, insts, items, bufA, bufB, theta, total;
 };
 
 Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
@@ -103,6 +104,8 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   o = align_up(o + sizeof(Slots) * (size_t)n);
   L.slots_save = o;  // the adjoint entry points park the slots here
   o = align_up(o + sizeof(Slots));
+  L.red = o;  // block partials of lbm_totals
+  o = align_up(o + sizeof(double) * 8 * (size_t)kTotalsBlocks);
   L.insts = o;
   o = align_up(o + sizeof(Inst) * (size_t)n);
   L.items = o;
@@ -343,7 +346,7 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   for (int i = 0; i < n; ++i) {
     if (h[i].cnt[vlbm::CNT_BAD]) {
       char buf[160];
-      snprintf(buf, sizeof(buf), "instance %d: %u cells of u0 are not admissible (rho <= 0 or p <= 0)",
+      snprintf(buf, sizeof(buf), "instance %d: %llu cells of u0 are not admissible (rho <= 0 or p <= 0)",
                i, h[i].cnt[vlbm::CNT_BAD]);
       delete c;
       return fail(nullptr, LBM_EPOSITIVITY, buf);
@@ -481,7 +484,7 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
   lbm_status st = read_slots(c, h);
   if (st != LBM_OK) return st;
   lbm_status res = LBM_OK;
-  unsigned bad = 0, guard = 0, bouchut = 0;
+  unsigned long long bad = 0, guard = 0, bouchut = 0;
   for (int i = 0; i < c->n_inst; ++i) {
     bad += h[i].cnt[vlbm::CNT_BAD];
     guard += h[i].cnt[vlbm::CNT_GUARD];
@@ -489,29 +492,24 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
   }
   char buf[160];
   if (bad) {
-    snprintf(buf, sizeof(buf), "%u non-admissible cells were produced", bad);
+    snprintf(buf, sizeof(buf), "%llu non-admissible cells were produced", bad);
     res = fail(c, LBM_EPOSITIVITY, buf);
   } else if (guard) {
-    snprintf(buf, sizeof(buf), "%u face states left the admissible set", guard);
+    snprintf(buf, sizeof(buf), "%llu face states left the admissible set", guard);
     res = fail(c, LBM_EGUARD, buf);
   } else if (bouchut) {
     res = fail(c, LBM_EBOUCHUT, "the fixed kinetic speed fell below the Bouchut bound");
   }
-  if (bad || guard || bouchut) {
-    for (auto& s : h) s.cnt[0] = s.cnt[1] = s.cnt[2] = s.cnt[3] = 0;
+  // every counter starts again from zero
+  bool any = false;
+  for (auto& s : h)
+    for (int k = 0; k < vlbm::CNT_N; ++k) {
+      any |= s.cnt[k] != 0;
+      s.cnt[k] = 0;
+    }
+  if (any) {
     st = write_slots(c, h);
     if (st != LBM_OK) return st;
-  } else {
-    // the limited-face counter is cleared too
-    bool any = false;
-    for (auto& s : h) {
-      any |= s.cnt[vlbm::CNT_LIMITED] != 0;
-      s.cnt[vlbm::CNT_LIMITED] = 0;
-    }
-    if (any) {
-      st = write_slots(c, h);
-      if (st != LBM_OK) return st;
-    }
   }
   return res;
 }
@@ -532,6 +530,40 @@ lbm_status lbm_diagnostics(lbm_ctx* c, int32_t inst, lbm_diag* d) {
   d->n_limited = s.cnt[vlbm::CNT_LIMITED];
   d->n_bad = s.cnt[vlbm::CNT_BAD];
   d->bouchut = (int32_t)s.cnt[vlbm::CNT_BOUCHUT];
+  d->n_lmp = s.cnt[vlbm::CNT_LMP];
+  return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_ctx* c, int32_t inst, double* out) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
+  if (!out) return fail(c, LBM_EINVAL, "output must be a host pointer to 4 doubles");
+  const Inst& in = c->insts[inst];
+  const long long n = (long long)in.nx * in.ny;
+  long long b = (n + 255) / 256;
+  const int blocks = (int)(b < kTotalsBlocks ? b : kTotalsBlocks);
+  double* part = (double*)(c->ws + c->lay.red);
+  hipError_t e = vlbm::launch_totals(in, c->plane, c->cur(), part, blocks, c->p.precision, c->stream);
+  std::vector<double> h((size_t)blocks * 8);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "totals");
+  for (int k = 0; k < 4; ++k) {
+    // combine the block partials in double-double (TwoSum, as on the device)
+    double hi = 0.0, lo = 0.0;
+    for (int q = 0; q < blocks; ++q) {
+      const double bh = h[((size_t)q * 4 + k) * 2], bl = h[((size_t)q * 4 + k) * 2 + 1];
+      const double s = hi + bh;
+      const double bp = s - hi;
+      double err = (hi - (s - bp)) + (bh - bp);
+      err += lo + bl;
+      const double nh = s + err;
+      lo = err - (nh - s);
+      hi = nh;
+    }
+    out[k] = hi + lo;
+  }
   return LBM_OK;
 }
 

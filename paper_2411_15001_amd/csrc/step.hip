@@ -111,6 +111,11 @@ __device__ __forceinline__ double theta_rho_lmp(double rs, double D, double kapp
   return num <= D ? 1.0 : num / D;
 }
 
+// Relative slack of the LMP check: the rounding of the update (float64
+// state: the slack the oracle uses; float32 state: a few float32 roundings).
+template <class T>
+constexpr double kLmpTol = sizeof(T) == 8 ? 1e-12 : 2e-6;
+
 // Margin of the division-free test below: c = 1 + 2^-30.
 constexpr double kFastMargin = 1.0 + 0x1p-30;
 
@@ -196,11 +201,12 @@ __device__ __forceinline__ void raise_lambda(unsigned long long* p, double lmax)
 
 // One lane per wave publishes the wave's wavespeed maximum and event counts.
 __device__ __forceinline__ void publish(Slots* sl, int slot, double lmax, unsigned n_bad,
-                                       unsigned n_guard, unsigned n_lim) {
+                                       unsigned n_guard, unsigned n_lim, unsigned n_lmp = 0) {
   raise_lambda(&sl->lam[slot], lmax);
-  if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], n_bad);
-  if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], n_guard);
-  if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], n_lim);
+  if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], (unsigned long long)n_bad);
+  if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], (unsigned long long)n_guard);
+  if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], (unsigned long long)n_lim);
+  if (n_lmp) atomicAdd(&sl->cnt[CNT_LMP], (unsigned long long)n_lmp);
 }
 
 // Wavespeed |v| + sqrt(gamma p / rho) of one state, or -1 if it is not
@@ -303,7 +309,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   if (xs == 0 && ys == 0 && lane == 0) {
     sl->lam[(A.slot + 2) % 3] = 0ull;
     sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
-    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
   }
 
   // plane q of this instance starts at base + q P; a cell is addressed by a
@@ -522,7 +528,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   if (xs == 0 && ys == 0 && lane == 0) {
     sl->lam[(A.slot + 2) % 3] = 0ull;
     sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
-    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1u);
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
   }
 
   const T* __restrict__ sbase = (const T*)A.src + in.off;
@@ -542,7 +548,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   C opr = C(0), opm = C(0), hpy = C(0);
 
   double lmax = 0.0;
-  unsigned n_bad = 0, n_guard = 0, n_lim = 0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_lmp = 0;
   // float64 state: the stores of a row are issued at the top of the next
   // iteration, right after its prefetch, so that they complete under that
   // iteration's compute rather than ahead of its wait for the prefetched
@@ -789,6 +795,10 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
         n_bad += 1;
       else
         lmax = vmax(lmax, l);
+      // LMP check: the stored density against the eq. (29) bounds of the
+      // cell (pmu, pnu: row L - 2), beyond the rounding of the update
+      const double r = (double)(T)fin[0], lo = (double)pmu, hi = (double)pnu;
+      n_lmp += (r < lo - kLmpTol<T> * fabs(lo)) || (r > hi + kLmpTol<T> * fabs(hi));
     }
     pmu = mu1;
     pnu = nu1;
@@ -816,11 +826,12 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_lmp += __shfl_xor(n_lmp, off, 64);
     n_bad += __shfl_xor(n_bad, off, 64);
     n_guard += __shfl_xor(n_guard, off, 64);
     n_lim += __shfl_xor(n_lim, off, 64);
   }
-  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim);
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp);
 }
 
 template <class T, class C, bool LMP, int WPE>
@@ -896,7 +907,61 @@ __global__ __launch_bounds__(256) void lambda_kernel(const Src* __restrict__ u, 
     lmax = vmax(vmax(wl[0], wl[1]), vmax(wl[2], wl[3]));
     bad = wb[0] + wb[1] + wb[2] + wb[3];
     raise_lambda(&sl->lam[slot], lmax);
-    if (bad) atomicAdd(&sl->cnt[CNT_BAD], bad);
+    if (bad) atomicAdd(&sl->cnt[CNT_BAD], (unsigned long long)bad);
+  }
+}
+
+// Error-free sum of two doubles (Knuth's TwoSum; exact without contraction):
+// s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+// (hi, lo) += (bh, bl) in double-double arithmetic.
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double bh, double bl) {
+  double s, e;
+  two_sum(hi, bh, s, e);
+  e += lo + bl;
+  hi = s + e;
+  lo = e - (hi - s);
+}
+
+// Totals of the conserved moments (rho, m1, m2, E) over n cells of the
+// moment slot, accumulated in double-double: one partial (hi, lo) per
+// component and block, part[block][component][2].
+template <class T>
+__global__ __launch_bounds__(256) void totals_kernel(const T* __restrict__ S, long long plane,
+                                                     long long n, double* __restrict__ part) {
+  double hi[4] = {0.0, 0.0, 0.0, 0.0}, lo[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dd_add(hi[k], lo[k], (double)S[k * plane + c], 0.0);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double oh = __shfl_xor(hi[k], off, 64), ol = __shfl_xor(lo[k], off, 64);
+      dd_add(hi[k], lo[k], oh, ol);
+    }
+  // every thread of the block reaches the barrier
+  __shared__ double wsum[4][4][2];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wsum[w][k][0] = hi[k];
+      wsum[w][k][1] = lo[k];
+    }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    double h = wsum[0][k][0], l = wsum[0][k][1];
+    for (int q = 1; q < 4; ++q) dd_add(h, l, wsum[q][k][0], wsum[q][k][1]);
+    part[((long long)blockIdx.x * 4 + k) * 2] = h;
+    part[((long long)blockIdx.x * 4 + k) * 2 + 1] = l;
   }
 }
 
@@ -1038,6 +1103,18 @@ hipError_t launch_moments(const Inst& in, long long plane, const void* S, double
   else
     hipLaunchKernelGGL((moments_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s,
                        (const float*)S + in.off, plane, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
+                         int blocks, int precision, hipStream_t s) {
+  const long long n = (long long)in.nx * in.ny;
+  if (precision == 0)
+    hipLaunchKernelGGL((totals_kernel<double>), dim3(blocks), dim3(256), 0, s,
+                       (const double*)S + in.off, plane, n, part);
+  else
+    hipLaunchKernelGGL((totals_kernel<float>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)S + in.off, plane, n, part);
   return hipGetLastError();
 }
 

@@ -26,9 +26,10 @@ struct Inst {
 struct alignas(128) Slots {
   unsigned long long lam[3]; // bit patterns of non-negative doubles
   double t[3];
-  unsigned int cnt[4];       // guard, limited, bad, bouchut (cumulative)
+  unsigned long long cnt[5]; // guard, limited, bad, bouchut, lmp (cumulative)
 };
-enum { CNT_GUARD = 0, CNT_LIMITED = 1, CNT_BAD = 2, CNT_BOUCHUT = 3 };
+enum { CNT_GUARD = 0, CNT_LIMITED = 1, CNT_BAD = 2, CNT_BOUCHUT = 3, CNT_LMP = 4, CNT_N = 5 };
+static_assert(sizeof(Slots) == 128, "one 128-byte record per instance");
 
 struct StepArgs {
   const void* src;
@@ -60,6 +61,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_i
                                int slot, int precision, hipStream_t s);
 hipError_t launch_moments(const Inst& in, long long plane, const void* S,
                           double* out, int precision, hipStream_t s);
+// Double-double partial totals of the moment slot, part[blocks][4][2]; the
+// grid is `blocks` workgroups of 256 threads.
+hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
+                         int blocks, int precision, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s);
 // Adjoint (adjoint.hip).

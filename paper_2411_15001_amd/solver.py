@@ -61,6 +61,9 @@ class Solver:
     def diagnostics(self):
         return B.lbm_diagnostics(self.ctx, 0).as_dict()
 
+    def totals(self):
+        return B.lbm_totals(self.ctx, 0)
+
     def get_state(self):
         import torch
 
@@ -136,6 +139,9 @@ class BatchSolver:
 
     def diagnostics(self, inst=0):
         return B.lbm_diagnostics(self.ctx, inst).as_dict()
+
+    def totals(self, inst=0):
+        return B.lbm_totals(self.ctx, inst)
 
     def autotune(self, cache=None):
         B.lbm_autotune(self.ctx, cache)
