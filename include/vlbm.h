@@ -184,8 +184,10 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
  * speed a^n held fixed at the values the forward step computes from U_n
  * (they are recomputed from U_n with the forward code, bit for bit):
  *   Ubar_n = (d S^{n+1} / d S^n)^T Ubar_np1.
- * All three are float64 states in the layout above (single instance,
- * LBM_FP64, periodic boundaries; LBM_ENOTSUP otherwise).  Uses the context's
+ * All three are float64 states in the layout above (single instance and
+ * LBM_FP64, LBM_ENOTSUP otherwise; ny <= 65535).  Periodic and outflow
+ * boundaries and sponge layers: with theta frozen the outflow ghosts only
+ * copy the edge cells, whose adjoint takes the copied reads back.  Uses the context's
  * workspace as scratch; does not change the context's own state.  Fully
  * asynchronous on the context's stream (no host synchronisation); Ubar_n
  * must not alias U_n or Ubar_np1, and U_n must not be a context buffer. */

@@ -1,4 +1,4 @@
-// Adjoint of one blended step and of the initialisation, FP64, periodic.
+// Adjoint of one blended step and of the initialisation, FP64.
 //
 // With theta and a held fixed, the step (eqs. (25), (27)) is, per cell c with
 // face factors tW, tE, tS, tN (faces i-1/2, i+1/2, j-1/2, j+1/2):
@@ -18,6 +18,15 @@
 //   ubar_3(x) = tN (ubar'(x) - g_3(N)),  ubar_4(x) = tS (ubar'(x) - g_4(S)).
 // The face factors come from the forward kernel run on the same state, so
 // they equal the forward step's bit for bit.
+//
+// Outflow boundaries (zero-gradient ghosts copying the nearest cell's whole
+// state): with theta frozen only the first ghost layer enters the map.  A
+// ghost neighbour is not an output, so its term above drops (g_k of that
+// neighbour = 0), and the edge cell reads its own state through the ghost:
+// at a west edge u_1'(x) = (1 + tW) M_1(u_x) - tW u_1(x), which adds
+// (1 + tW) J_{M_1}^T g_1(x) to ubar(x) and -tW g_1(x) to ubar_1(x); likewise
+// M_2 / tE at an east edge, M_3 / tS at a south edge, M_4 / tN at a north
+// edge.
 
 #include "vlbm_internal.h"
 
@@ -79,27 +88,36 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
   const double r2a = 1.0 / (2.0 * a);
   const int iw = i == 0 ? nx - 1 : i - 1, ie = i == nx - 1 ? 0 : i + 1;
   const int js = j == 0 ? ny - 1 : j - 1, jn = j == ny - 1 ? 0 : j + 1;
+  // neighbours that are outflow ghosts
+  const bool gw = sc.bc_x == 1 && i == 0, ge = sc.bc_x == 1 && i == nx - 1;
+  const bool gs = sc.bc_y == 1 && j == 0, gn = sc.bc_y == 1 && j == ny - 1;
   const long long cX = (long long)j * nx + i;
   const long long cW = (long long)j * nx + iw, cE = (long long)j * nx + ie;
   const long long cS = (long long)js * nx + i, cN = (long long)jn * nx + i;
   const double tW = tx[(long long)j * (nx + 1) + i], tE = tx[(long long)j * (nx + 1) + i + 1];
   const double tS = ty[(long long)j * nx + i], tN = ty[(long long)(j + 1) * nx + i];
-  double u[4], ub[4], g1[4], g2[4], g3[4], g4[4];
+  // g1..g4: adjoint reaching u_k' of the neighbour that reads this cell
+  // (0 for a ghost); h1..h4: this cell's own g_k, read back through a ghost
+  double u[4], ub[4], g1[4], g2[4], g3[4], g4[4], h1[4], h2[4], h3[4], h4[4];
   for (int c = 0; c < 4; ++c) {
     u[c] = U[c * P + cX];
     ub[c] = B1[c * P + cX];
-    g1[c] = B1[(4 + c) * P + cE] + B1[c * P + cE];
-    g2[c] = B1[(8 + c) * P + cW] + B1[c * P + cW];
-    g3[c] = B1[(12 + c) * P + cN] + B1[c * P + cN];
-    g4[c] = B1[(16 + c) * P + cS] + B1[c * P + cS];
+    g1[c] = ge ? 0.0 : B1[(4 + c) * P + cE] + B1[c * P + cE];
+    g2[c] = gw ? 0.0 : B1[(8 + c) * P + cW] + B1[c * P + cW];
+    g3[c] = gn ? 0.0 : B1[(12 + c) * P + cN] + B1[c * P + cN];
+    g4[c] = gs ? 0.0 : B1[(16 + c) * P + cS] + B1[c * P + cS];
+    h1[c] = gw ? B1[(4 + c) * P + cX] + ub[c] : 0.0;
+    h2[c] = ge ? B1[(8 + c) * P + cX] + ub[c] : 0.0;
+    h3[c] = gs ? B1[(12 + c) * P + cX] + ub[c] : 0.0;
+    h4[c] = gn ? B1[(16 + c) * P + cX] + ub[c] : 0.0;
   }
   const Jac J = jac_of(u, sc.gamma);
   double z1[4], z2[4], z3[4], z4[4];
   for (int c = 0; c < 4; ++c) {
-    z1[c] = (1.0 + tE) * g1[c] - tE * ub[c];
-    z2[c] = (1.0 + tW) * g2[c] - tW * ub[c];
-    z3[c] = (1.0 + tN) * g3[c] - tN * ub[c];
-    z4[c] = (1.0 + tS) * g4[c] - tS * ub[c];
+    z1[c] = (1.0 + tE) * g1[c] - tE * ub[c] + (1.0 + tW) * h1[c];
+    z2[c] = (1.0 + tW) * g2[c] - tW * ub[c] + (1.0 + tE) * h2[c];
+    z3[c] = (1.0 + tN) * g3[c] - tN * ub[c] + (1.0 + tS) * h3[c];
+    z4[c] = (1.0 + tS) * g4[c] - tS * ub[c] + (1.0 + tN) * h4[c];
   }
   double dx[4], dy[4], ax[4], by[4];
   for (int c = 0; c < 4; ++c) {
@@ -110,10 +128,10 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
   Bt(J, dy, by);
   for (int c = 0; c < 4; ++c) {
     B0[c * P + cX] = sc.alpha * ub[c] + w * (z1[c] + z2[c] + z3[c] + z4[c]) + r2a * (ax[c] + by[c]);
-    B0[(4 + c) * P + cX] = tE * (ub[c] - g1[c]);
-    B0[(8 + c) * P + cX] = tW * (ub[c] - g2[c]);
-    B0[(12 + c) * P + cX] = tN * (ub[c] - g3[c]);
-    B0[(16 + c) * P + cX] = tS * (ub[c] - g4[c]);
+    B0[(4 + c) * P + cX] = tE * (ub[c] - g1[c]) - tW * h1[c];
+    B0[(8 + c) * P + cX] = tW * (ub[c] - g2[c]) - tE * h2[c];
+    B0[(12 + c) * P + cX] = tN * (ub[c] - g3[c]) - tS * h3[c];
+    B0[(16 + c) * P + cX] = tS * (ub[c] - g4[c]) - tN * h4[c];
   }
 }
 

@@ -752,9 +752,6 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
-  if (c->p.bc_x != LBM_BC_PERIODIC || c->p.bc_y != LBM_BC_PERIODIC)
-    return fail(c, LBM_ENOTSUP, "the adjoint supports periodic boundaries only");
-  if (c->p.sponge > 0) return fail(c, LBM_ENOTSUP, "the adjoint does not support sponge layers");
   if (!U || !Ub1 || !Ub0) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())

@@ -171,6 +171,47 @@ def test_step_adjoint_dot_product(gpu, lims):
     assert info.n_limited > 0
 
 
+ADJ_BC_CASES = [
+    # nx, ny, bc_x, bc_y, sponge, limiters
+    (64, 64, 1, 1, 0, 1 | 8),
+    (61, 40, 1, 0, 0, 1 | 2 | 8),
+    (50, 70, 0, 1, 3, 1 | 8),
+    (72, 66, 1, 1, 4, 1 | 2 | 8),
+    (2, 16, 1, 1, 0, 1 | 8),
+    (1, 9, 1, 0, 0, 1 | 8),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_BC_CASES, ids=lambda c: "%dx%d-bc%d%d-s%d-l%d" % c)
+def test_step_adjoint_boundaries(gpu, case):
+    """Outflow boundaries (one or both axes), sponge layers, ragged and
+    degenerate widths: <J v, w> from the oracle's complex-step tangent of the
+    step (theta and a frozen at the forward values, its ghosts built the same
+    way) equals <v, J^T w> from lbm_step_adjoint."""
+    nx, ny, bcx, bcy, sponge, lims = case
+    u0 = np.ascontiguousarray(cases.riemann4(max(nx, ny), seed=7)[:, :ny, :nx])
+    cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / max(nx, ny), limiters=lims, a_beta=1.1,
+                        bc_x=bcx, bc_y=bcy, sponge=sponge)
+    S, _ = oracle.init(cfg, u0)
+    S, _, _, _ = oracle.run(cfg, S, 12)
+    _, tx, ty, info = oracle.step(cfg, S)
+    rng = np.random.default_rng(11)
+    kw = dict(dx=1.0 / max(nx, ny), limiters=lims, a_beta=1.1, bc_x=bcx, bc_y=bcy, sponge=sponge)
+    s = solver(u0, **kw)
+    Ut = gpu.from_numpy(S).cuda()
+    for _ in range(2):
+        v = rng.normal(size=S.shape)
+        w = rng.normal(size=S.shape)
+        h = 1e-30
+        _, im = oracle.step_frozen_cs(cfg, S, h * v, tx, ty, info.a)
+        jv = im / h
+        out = gpu.empty_like(Ut)
+        B.lbm_step_adjoint(s.ctx, Ut, gpu.from_numpy(w).cuda(), out)
+        lhs, rhs = _dot(jv, w), _dot(v, out.cpu().numpy())
+        assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(jv) * np.linalg.norm(w), (lhs, rhs)
+    s.close()
+
+
 @pytest.mark.parametrize("fixed_a", [False, True])
 @pytest.mark.parametrize("lims", [1 | 8, 1 | 2 | 8])
 def test_step_adjoint_theta_equals_recomputed(gpu, lims, fixed_a):
@@ -278,18 +319,21 @@ def test_rollout_gradient_finite_differences(gpu):
     assert worst <= 1e-6
 
 
-def test_rollout_gradient_vs_oracle_jvp(gpu):
+@pytest.mark.parametrize("bc", [0, 1])
+def test_rollout_gradient_vs_oracle_jvp(gpu, bc):
     """<grad L, d> from the GPU adjoint equals the oracle's complex-step
     directional derivative of the same rollout (theta and a frozen at the
-    oracle's forward values) on a 64^2 grid with limited faces."""
+    oracle's forward values) on a 64^2 grid with limited faces, periodic or
+    with outflow boundaries on both axes."""
     from paper_2411_15001_amd.autograd import rollout
 
     n, steps = 64, 30
     u0 = cases.riemann4(n, seed=6)
     lam0 = oracle.lam(oracle.Config(nx=n, ny=n), u0)[0]
     a_fixed = 6.0 * lam0  # lambda grows by ~13% over the run; keeps a >= 4 lambda
-    cfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, a_mode=oracle.A_FIXED, a_fixed=a_fixed)
-    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=a_fixed, limiters=1 | 2 | 8)
+    cfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, a_mode=oracle.A_FIXED, a_fixed=a_fixed,
+                        bc_x=bc, bc_y=bc)
+    kw = dict(a_mode=B.LBM_A_FIXED, a_fixed=a_fixed, limiters=1 | 2 | 8, bc_x=bc, bc_y=bc)
     rng = np.random.default_rng(5)
     wgt = rng.normal(size=(n, n))
     u0t = gpu.from_numpy(u0).cuda().requires_grad_(True)

@@ -80,6 +80,8 @@ THETA_CASES = [
     (3, 17, 1 | 2 | 8, 2, 0, 0, 0, 5, "riemann"),
     (300, 130, 2 | 8, 2, 1, 1, 3, 6, "riemann"),
     (257, 65, 4 | 8, 2, 0, 0, 0, 6, "laxliu"),
+    (1, 9, 1 | 8, 2, 1, 0, 0, 4, "riemann"),
+    (2, 16, 1 | 2 | 8, 2, 1, 1, 0, 4, "riemann"),
 ]
 
 
