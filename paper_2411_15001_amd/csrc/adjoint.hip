@@ -73,6 +73,9 @@ __device__ __forceinline__ double kinetic_speed(const Scheme& s, const Slots* sl
   return (s.a_mode == 1) ? s.a_fixed : 2.0 * s.beta * lam / (1.0 - s.alpha);
 }
 
+// EDGES: the context has an outflow axis (the edge terms above); periodic
+// contexts run without them.
+template <bool EDGES>
 __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, int ny, long long P,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ B1,
@@ -89,8 +92,8 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
   const int iw = i == 0 ? nx - 1 : i - 1, ie = i == nx - 1 ? 0 : i + 1;
   const int js = j == 0 ? ny - 1 : j - 1, jn = j == ny - 1 ? 0 : j + 1;
   // neighbours that are outflow ghosts
-  const bool gw = sc.bc_x == 1 && i == 0, ge = sc.bc_x == 1 && i == nx - 1;
-  const bool gs = sc.bc_y == 1 && j == 0, gn = sc.bc_y == 1 && j == ny - 1;
+  const bool gw = EDGES && sc.bc_x == 1 && i == 0, ge = EDGES && sc.bc_x == 1 && i == nx - 1;
+  const bool gs = EDGES && sc.bc_y == 1 && j == 0, gn = EDGES && sc.bc_y == 1 && j == ny - 1;
   const long long cX = (long long)j * nx + i;
   const long long cW = (long long)j * nx + iw, cE = (long long)j * nx + ie;
   const long long cS = (long long)js * nx + i, cN = (long long)jn * nx + i;
@@ -170,8 +173,12 @@ hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane
                                const Slots* slots, int slot, hipStream_t s) {
   const dim3 block(256);
   const dim3 grid((in.nx + 255) / 256, in.ny);
-  hipLaunchKernelGGL(adjoint_step_kernel, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1, Ub0,
-                     tx, ty, slots, slot);
+  if (sc.bc_x == 1 || sc.bc_y == 1)
+    hipLaunchKernelGGL(adjoint_step_kernel<true>, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1,
+                       Ub0, tx, ty, slots, slot);
+  else
+    hipLaunchKernelGGL(adjoint_step_kernel<false>, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1,
+                       Ub0, tx, ty, slots, slot);
   return hipGetLastError();
 }
 

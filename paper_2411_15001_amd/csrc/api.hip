@@ -142,7 +142,6 @@ struct lbm_ctx {
   int strip_rows = 64;
   int waves = 4;
   int xcd = 1;
-  int persistent_groups = 0;  // > 0: persistent launch with this many groups
   std::string err;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
 
@@ -210,9 +209,11 @@ lbm_status upload_tables(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// One wave per strip, for single instances and ensembles alike: a persistent
+// grid striding over the strips of an ensemble measured 1-4% slower than
+// letting the dispatcher place one wave per strip.
 int compute_groups(const lbm_ctx* c) {
   long long g = (c->n_items + c->waves - 1) / c->waves;
-  if (c->persistent_groups > 0 && g > c->persistent_groups) g = c->persistent_groups;
   if (c->xcd) g = (g + 7) / 8 * 8;
   return (int)g;
 }
@@ -312,12 +313,6 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
     off += (long long)nx[i] * ny[i];
   }
   c->plane = off;
-  if (n > 1) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    c->persistent_groups = cus * 4;
-  }
   c->strip_rows = default_strip_rows(c);
   build_items(c);
   lbm_status st = upload_tables(c);
