@@ -138,7 +138,15 @@ lbm_status lbm_init_batch(const lbm_params* p, int32_t n, const int32_t* nx,
                           void* stream, lbm_ctx** out);
 
 /* nsteps time steps (eqs. (25), (27) with the limiters of Section 3), one
- * kernel launch each, asynchronous, no host synchronisation. */
+ * kernel launch each, asynchronous, no host synchronisation.  The launches
+ * may be recorded into a caller's hipGraph; each bakes in the step's phase
+ * (lambda slot step mod 3, state buffer step mod 2) and the context counts
+ * the steps once, at record time.  A recording of a multiple of 6 steps
+ * returns to its starting phase, so it can be replayed any number of times
+ * (the state, lambda and t follow the replays; the host-side step count
+ * reported by lbm_diagnostics does not);
+ * other recordings are replayed once.  lbm_step_graph does this
+ * bookkeeping itself. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* Same steps, replayed from a hipGraph of the launches (captured on first use
