@@ -544,7 +544,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   C qM3[4] = {}, qd3[4] = {}, qP[4] = {};               // row L - 2
   // edge lanes: the halo column's u and u_1 / u_2 of row L - 1, rho and m_1
   // of the outer column in row L - 1, the halo cell's y-face density at L - 3/2
-  C hpu[4] = {}, hpk[4] = {};
+  C hpu[4] = {}, hpk[4] = {}, hpf[4] = {}, hpg[4] = {};
   C opr = C(0), opm = C(0), hpy = C(0);
 
   double lmax = 0.0;
@@ -652,8 +652,6 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
     }
 
     // ---- row L - 1: the halo column's Maxwellians, the west edge face
-    C hpf[4], hpg[4];
-    fluxes(hpu, K.gm1, hpf, hpg);
     C hM[4], hd[4], usw[4], dFw[4], pd2[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -816,6 +814,8 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       pdG[c] = dG[c];
       hpu[c] = hu[c];
       hpk[c] = hk[c];
+      hpf[c] = hf[c];
+      hpg[c] = hg[c];
 #pragma unroll
       for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
     }
