@@ -169,6 +169,23 @@ def cpu_model():
     return None
 
 
+def kernel_source_digest():
+    """sha256 of the step kernel's source (step.hip + vlbm_internal.h) with
+    comments and white space removed, so that the recorded counters stay
+    attached to the kernel through edits of its comments only."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for name in ("step.hip", "vlbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2411_15001_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def traffic_for(key):
     """Measured HBM bytes per launch (rocprofv3 counters) of the workload and
     form `key` (e.g. "blast8192_fp32"), if recorded for the current kernel
@@ -179,14 +196,8 @@ def traffic_for(key):
     except OSError:
         return None
     lib = os.path.join(ROOT, "paper_2411_15001_amd", "libvlbm.so")
-    import hashlib
-
-    h = hashlib.sha256()
-    for name in ("step.hip", "vlbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2411_15001_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
     entry = rec.get(key)
-    if not entry or entry.get("source_sha256") != h.hexdigest() or not os.path.exists(lib):
+    if not entry or entry.get("source_sha256") != kernel_source_digest() or not os.path.exists(lib):
         return None
     return entry.get("bytes_per_launch")
 

@@ -1,18 +1,21 @@
 // Fused collide-limit-stream step of the blended D2Q5 vectorial lattice
 // Boltzmann scheme (Wissocq, Liu, Abgrall), gfx950.
 //
-// Work decomposition.  A wave owns a strip of 64 consecutive columns and H
-// consecutive rows of one instance and marches up the strip one row at a
-// time; lane l holds column x0 + l.  x-neighbours are exchanged with
-// wave-wide lane shifts; y-neighbours are the rows the lane already holds in
-// registers from the previous iterations.  No LDS and no barrier is used.
-// The blending factor of an x-face i+1/2 needs the density bounds of cells i
-// and i+1, which need the face states of their own faces, so the LMP variant
-// has a halo of R = 2 lanes on each side (60 output columns per wave) and the
-// other variants R = 1 (62 columns).  Along y the march runs two rows ahead
-// of the row it completes (the same dependency), so a strip reads H + 4 rows.
+// Work decomposition.  A wave owns an aligned strip of 64 consecutive
+// columns (x0 = 64 xs) and H consecutive rows of one instance and marches up
+// the strip one row at a time; lane l holds column x0 + l and every lane
+// produces output.  x-neighbours are exchanged with wave-wide lane shifts;
+// the two edge lanes also load the halo column beside the strip and evaluate
+// the faces and bounds that reach across it.  y-neighbours are the rows the
+// lane already holds in registers from the previous iterations.  No LDS and
+// no barrier is used.
 //
-// Pipeline of one iteration (newest row L loaded):
+// Without density bounds (PP, pressure, unlimited, first order) both face
+// factors of a row are known as soon as it arrives, so the march completes
+// row L - 1 when row L arrives and reads H + 2 rows.  With LMP / RLMP bounds
+// the blending factor of a face needs the bounds of both its cells, and a
+// cell's bounds need its upper y-face, so the march lags two rows and reads
+// H + 4.  Pipeline of one LMP iteration (newest row L loaded):
 //   row L     : Maxwellians and d_k (Example 1), x-face state u*_{i+1/2} and
 //               Delta F_{i+1/2} (eqs. (12), (22)), y-face L-1/2 (u*, Delta G);
 //   row L - 1 : density bounds (eq. (29)), theta of its x-face i+1/2 and of
