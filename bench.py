@@ -98,9 +98,9 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     prec = B.LBM_FP32_STATE if form == "fp32" else B.LBM_FP64
     s = Solver(u0t, precision=prec, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE)
     if autotune:
-        rows, waves = s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
+        launch = s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
     else:
-        rows, waves = B.lbm_get_launch(s.ctx)
+        launch = s.launch()
     tot0 = s.totals()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -129,7 +129,7 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     achieved = BYTES_PER_CELL[form] * cells / (avg_ms * 1e-3) / 1e9
     return {
         "value": glups, "ms_per_step": avg_ms, "wall_s": wall, "status": int(st),
-        "launch": {"strip_rows": rows, "waves_per_group": waves},
+        "launch": {"strip_rows": launch[0], "waves_per_group": launch[1], "groups_per_cu": launch[2]},
         "diag": {"t": d["t"], "lambda": d["lam"], "n_bad": d["n_bad"], "n_guard": d["n_guard"]},
         "conservation_drift": drift,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -186,10 +186,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def traffic_for(key):
+def traffic_for(key, launch):
     """Measured HBM bytes per launch (rocprofv3 counters) of the workload and
     form `key` (e.g. "blast8192_fp32"), if recorded for the current kernel
-    source."""
+    source and the same launch shape (strip rows, waves per group, groups per
+    CU): the re-read halo rows depend on the strip height."""
     try:
         with open(PMC_FILE) as f:
             rec = json.load(f)
@@ -198,6 +199,8 @@ def traffic_for(key):
     lib = os.path.join(ROOT, "paper_2411_15001_amd", "libvlbm.so")
     entry = rec.get(key)
     if not entry or entry.get("source_sha256") != kernel_source_digest() or not os.path.exists(lib):
+        return None
+    if list(entry.get("launch", [])) != list(launch):
         return None
     return entry.get("bytes_per_launch")
 
@@ -333,8 +336,8 @@ def bench_rarefaction(a):
           {"workload": "near-vacuum double rarefaction 2048x2048, outflow, PP + LMP + pressure, "
                        "a = 4 lambda, fp64 form", "grid": [n, n]},
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("rarefaction%d_fp64" % n)},
-          status=int(st), launch=list(B.lbm_get_launch(s.ctx)),
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("rarefaction%d_fp64" % n, s.launch())},
+          status=int(st), launch=list(s.launch()),
           **({} if a.no_cpu else {"cpu_baseline": cpu_rarefaction(n)}))
     s.close()
 
@@ -369,7 +372,7 @@ def bench_batch(a):
     torch.cuda.synchronize()
     ms = _timed(lambda: bs.step_graph(a.steps), a.steps)
     st = bs.moments(0, check=False)[1]
-    launch = B.lbm_get_launch(bs.ctx)
+    launch = bs.launch()
     bs.close()
     avg = ms / a.steps
     ach = 160.0 * cells / (avg * 1e-3) / 1e9
@@ -381,7 +384,7 @@ def bench_batch(a):
         cb = BatchSolver([u0s[i] for i in idx], **kw)
         cb.step(5)
         cms = _timed(lambda: cb.step(100), 100) / 100
-        cl = list(B.lbm_get_launch(cb.ctx))
+        cl = list(cb.launch())
         cb.close()
         cc = len(idx) * side * side
         per_class[str(side)] = {"instances": len(idx), "cells": cc, "ms_per_step": cms, "launch": cl,
@@ -471,7 +474,9 @@ def main():
     rho = {}
     for form in a.forms.split(","):
         forms[form], rho[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
-        forms[form]["roofline"]["traffic"] = traffic_for("blast%d_%s" % (a.n, form))
+        L = forms[form]["launch"]
+        forms[form]["roofline"]["traffic"] = traffic_for(
+            "blast%d_%s" % (a.n, form), [L["strip_rows"], L["waves_per_group"], L["groups_per_cu"]])
         print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
             form, forms[form]["value"], forms[form]["ms_per_step"],
             100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)

@@ -218,13 +218,16 @@ lbm_status lbm_step_adjoint_theta(lbm_ctx* ctx, const double* U_n_dev,
 lbm_status lbm_init_adjoint(lbm_ctx* ctx, const double* u0_dev,
                             const double* Ubar0_dev, double* u0bar_dev);
 
-/* Times the step kernel for the candidate strip heights and waves per
- * workgroup on the context's own problem, keeps the fastest and records it in
- * a JSON cache file keyed by problem shape (NULL path = no file); a cached
- * entry is used without timing.  The timed launches read the current state
- * and write the other buffer, and the slots (lambda, t, counters) are
- * restored, so the context's state and step count are unchanged.
- * Synchronises. */
+/* Times the step kernel for the candidate strip heights, waves per workgroup
+ * and grids (one wave per strip, or a persistent grid of 1, 2 or 4
+ * workgroups per compute unit) on the context's own problem and keeps the
+ * fastest: a first pass times every candidate, then the four fastest are
+ * timed again, best of three.  The choice is recorded in a JSON cache file
+ * keyed by problem shape (NULL path = no file) as [rows, waves, groups per
+ * CU]; a cached entry is used without timing (an entry of two values has no
+ * persistent grid).  The timed launches read the current state and write the
+ * other buffer, and the slots (lambda, t, counters) are restored, so the
+ * context's state and step count are unchanged.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
 
 /* Launch shape of the step kernel: rows per strip in [4, 4096] and waves
@@ -235,6 +238,16 @@ lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
  * the shape drops captured graphs. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t strip_rows, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* waves_per_group);
+
+/* Grid of the step kernel.  groups_per_cu = 0 (the default) launches one wave
+ * per strip; k in [1, 32] launches a persistent grid of at most k workgroups
+ * per compute unit of the device (rounded up to a multiple of 8, never more
+ * than one wave per strip), whose waves loop over the strips of all
+ * instances.  Results do not depend on the grid.  LBM_EINVAL outside [0, 32];
+ * changing the grid drops captured graphs.  lbm_get_grid also returns the
+ * number of workgroups a step launch uses (groups may be NULL). */
+lbm_status lbm_set_grid(lbm_ctx* ctx, int32_t groups_per_cu);
+lbm_status lbm_get_grid(const lbm_ctx* ctx, int32_t* groups_per_cu, int32_t* groups);
 
 const char* lbm_status_string(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* ctx);

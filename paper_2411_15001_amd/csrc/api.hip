@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <tuple>
@@ -18,6 +19,7 @@ using vlbm::Slots;
 namespace {
 
 constexpr int kMinStripRows = 4;  // bounds the work-item table in the workspace
+constexpr int kMaxGridPerCu = 32;
 constexpr int kTotalsBlocks = 1024;  // workgroups of the totals reduction
 constexpr int kMaxStripRows = 4096;
 constexpr size_t kAlign = 256;
@@ -142,6 +144,8 @@ struct lbm_ctx {
   int strip_rows = 64;
   int waves = 4;
   int xcd = 1;
+  int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
+  int n_cu = 256;       // compute units of the context's device
   std::string err;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
 
@@ -209,11 +213,15 @@ lbm_status upload_tables(lbm_ctx* c) {
   return LBM_OK;
 }
 
-// One wave per strip, for single instances and ensembles alike: a persistent
-// grid striding over the strips of an ensemble measured 1-4% slower than
-// letting the dispatcher place one wave per strip.
+// Workgroups of a step launch.  By default one wave per strip, for single
+// instances and ensembles alike; with grid_per_cu = k > 0 a persistent grid
+// of k workgroups per compute unit whose waves stride over the strips (the
+// kernel loops over its work items either way).  On the 8192^2 blast and the
+// 256-instance ensemble the persistent grid measured 1-4% slower; the
+// autotuner times both.
 int compute_groups(const lbm_ctx* c) {
   long long g = (c->n_items + c->waves - 1) / c->waves;
+  if (c->grid_per_cu > 0) g = std::min(g, (long long)c->grid_per_cu * c->n_cu);
   if (c->xcd) g = (g + 7) / 8 * 8;
   return (int)g;
 }
@@ -313,6 +321,12 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
     off += (long long)nx[i] * ny[i];
   }
   c->plane = off;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->n_cu = cus;
+  }
   c->strip_rows = default_strip_rows(c);
   build_items(c);
   lbm_status st = upload_tables(c);
@@ -615,13 +629,31 @@ lbm_status lbm_get_launch(const lbm_ctx* c, int32_t* rows, int32_t* waves) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_grid(lbm_ctx* c, int32_t groups_per_cu) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (groups_per_cu < 0 || groups_per_cu > kMaxGridPerCu)
+    return fail(c, LBM_EINVAL, "groups per compute unit must lie in [0, 32]");
+  c->grid_per_cu = groups_per_cu;
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return LBM_OK;
+}
+
+lbm_status lbm_get_grid(const lbm_ctx* c, int32_t* groups_per_cu, int32_t* groups) {
+  if (!c || !groups_per_cu) return LBM_EINVAL;
+  *groups_per_cu = c->grid_per_cu;
+  if (groups) *groups = compute_groups(c);
+  return LBM_OK;
+}
+
 lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   char key[160];
   long long cells = c->plane;
   snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d", c->n_inst, c->insts[0].nx,
            c->insts[0].ny, cells, c->p.precision, c->p.limiters, c->p.order);
-  // cache lookup: a flat JSON object {"key": [rows, waves], ...}
+  // cache lookup: a flat JSON object {"key": [rows, waves, groups per CU], ...}
+  // (entries of two values have no persistent grid)
   std::string text;
   if (path) {
     FILE* f = fopen(path, "rb");
@@ -633,9 +665,13 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
       const std::string k = std::string("\"") + key + "\"";
       size_t pos = text.find(k);
       if (pos != std::string::npos) {
-        int rows = 0, waves = 0;
-        if (sscanf(text.c_str() + pos + k.size(), " : [ %d , %d ]", &rows, &waves) == 2)
-          return lbm_set_launch(c, rows, waves);
+        int rows = 0, waves = 0, grid = 0;
+        const int got = sscanf(text.c_str() + pos + k.size(), " : [ %d , %d , %d ]", &rows, &waves, &grid);
+        if (got >= 2) {
+          lbm_status st = lbm_set_launch(c, rows, waves);
+          if (st == LBM_OK) st = lbm_set_grid(c, got == 3 ? grid : 0);
+          return st;
+        }
       }
     }
   }
@@ -644,45 +680,82 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   if (st != LBM_OK) return st;
   const int rows_c[] = {4, 8, 16, 32, 64, 128, 256};
   const int waves_c[] = {1, 2, 4};
+  const int grid_c[] = {0, 1, 2, 4};  // one wave per strip, or persistent grids
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, LBM_EDEVICE, "hipEventCreate");
   float best = 1e30f;
-  int best_r = c->strip_rows, best_w = c->waves;
+  int best_r = c->strip_rows, best_w = c->waves, best_g = c->grid_per_cu;
+  // average time of one launch of the shape (r, w, gpc); launches all read the
+  // current state and write the other buffer, so the state is not advanced
+  auto time_shape = [&](int r, int w, int gpc, float work_ms, float& ms) -> lbm_status {
+    lbm_status s2 = lbm_set_launch(c, r, w);
+    if (s2 == LBM_OK) s2 = lbm_set_grid(c, gpc);
+    if (s2 != LBM_OK) return s2;
+    ms = -1.0f;
+    // a persistent grid no smaller than one wave per strip is the same launch
+    if (gpc > 0 && (long long)gpc * c->n_cu * w >= c->n_items) return LBM_OK;
+    vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
+    // one timed launch sizes the repetition count to about work_ms of work
+    hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) e = vlbm::launch_step(a, c->p.precision, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    int reps = t > 0.0f ? (int)(work_ms / t) : 64;
+    reps = reps < 2 ? 2 : (reps > 256 ? 256 : reps);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = vlbm::launch_step(a, c->p.precision, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune");
+    ms = t / reps;
+    return LBM_OK;
+  };
+  // first pass: every candidate with about 4 ms of launches; second pass: the
+  // four fastest again, three times each with about 12 ms, interleaved, best
+  // of three (shapes within a few percent of each other are told apart)
+  struct Cand {
+    float ms;
+    int r, w, g;
+  };
+  std::vector<Cand> cands;
+  auto bail = [&](lbm_status s2) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s2;
+  };
   for (int r : rows_c) {
     if (r > 2 * c->insts[0].ny && r != 16) continue;
     for (int w : waves_c) {
-      st = lbm_set_launch(c, r, w);
-      if (st != LBM_OK) break;
-      // time launches that all read the current state and write the other
-      // buffer (the state is not advanced)
-      vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
-      // one timed launch sizes the repetition count to about 4 ms of work
-      hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
-      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-      if (e == hipSuccess) e = vlbm::launch_step(a, c->p.precision, c->stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      int reps = ms > 0.0f ? (int)(4.0f / ms) : 64;
-      reps = reps < 2 ? 2 : (reps > 64 ? 64 : reps);
-      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-      for (int k = 0; k < reps && e == hipSuccess; ++k) e = vlbm::launch_step(a, c->p.precision, c->stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess) ms /= reps;
-      if (e != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return hip_fail(c, e, "autotune");
+      for (int gpc : grid_c) {
+        float ms = -1.0f;
+        st = time_shape(r, w, gpc, 4.0f, ms);
+        if (st != LBM_OK) return bail(st);
+        if (ms >= 0.0f) cands.push_back({ms, r, w, gpc});
       }
-      if (ms < best) {
-        best = ms;
-        best_r = r;
-        best_w = w;
-      }
+    }
+  }
+  std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  if (cands.size() > 4) cands.resize(4);
+  for (Cand& k : cands) k.ms = 1e30f;
+  for (int round = 0; round < 3; ++round) {
+    for (Cand& k : cands) {
+      float ms = -1.0f;
+      st = time_shape(k.r, k.w, k.g, 12.0f, ms);
+      if (st != LBM_OK) return bail(st);
+      k.ms = std::min(k.ms, ms);
+    }
+  }
+  for (const Cand& k : cands) {
+    if (k.ms < best) {
+      best = k.ms;
+      best_r = k.r;
+      best_w = k.w;
+      best_g = k.g;
     }
   }
   (void)hipEventDestroy(e0);
@@ -690,13 +763,14 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   st = write_slots(c, saved);
   if (st != LBM_OK) return st;
   st = lbm_set_launch(c, best_r, best_w);
+  if (st == LBM_OK) st = lbm_set_grid(c, best_g);
   if (st != LBM_OK) return st;
   if (path) {
     // append the entry to the flat JSON object
     std::string body = text;
     size_t end = body.rfind('}');
     char entry[256];
-    snprintf(entry, sizeof(entry), "\"%s\": [%d, %d]", key, best_r, best_w);
+    snprintf(entry, sizeof(entry), "\"%s\": [%d, %d, %d]", key, best_r, best_w, best_g);
     if (end == std::string::npos) {
       body = std::string("{\n  ") + entry + "\n}\n";
     } else {

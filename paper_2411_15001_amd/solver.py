@@ -75,11 +75,19 @@ class Solver:
         B.lbm_set_state(self.ctx, s.contiguous())
 
     def autotune(self, cache=None):
+        """Pick (strip rows, waves per workgroup, groups per CU) by timing;
+        returns the chosen launch."""
         B.lbm_autotune(self.ctx, cache)
-        return B.lbm_get_launch(self.ctx)
+        return self.launch()
 
-    def set_launch(self, strip_rows=0, waves_per_group=0):
+    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None):
         B.lbm_set_launch(self.ctx, strip_rows, waves_per_group)
+        if groups_per_cu is not None:
+            B.lbm_set_grid(self.ctx, groups_per_cu)
+
+    def launch(self):
+        """(strip rows, waves per workgroup, groups per CU; 0 = one wave per strip)"""
+        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0],)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -144,11 +152,19 @@ class BatchSolver:
         return B.lbm_totals(self.ctx, inst)
 
     def autotune(self, cache=None):
+        """Pick (strip rows, waves per workgroup, groups per CU) by timing;
+        returns the chosen launch."""
         B.lbm_autotune(self.ctx, cache)
-        return B.lbm_get_launch(self.ctx)
+        return self.launch()
 
-    def set_launch(self, strip_rows=0, waves_per_group=0):
+    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None):
         B.lbm_set_launch(self.ctx, strip_rows, waves_per_group)
+        if groups_per_cu is not None:
+            B.lbm_set_grid(self.ctx, groups_per_cu)
+
+    def launch(self):
+        """(strip rows, waves per workgroup, groups per CU; 0 = one wave per strip)"""
+        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0],)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -30,6 +30,12 @@ def Solver(*a, **k):
     return S(*a, **k)
 
 
+def BatchSolver(*a, **k):
+    from paper_2411_15001_amd.solver import BatchSolver as S
+
+    return S(*a, **k)
+
+
 def rel_err(a, b):
     a = a.reshape(a.shape[0], -1)
     b = b.reshape(b.shape[0], -1)
@@ -324,6 +330,49 @@ def test_determinism(lims):
         b.close()
 
 
+@pytest.mark.parametrize("prec,lims", [(B.LBM_FP64, 1 | 8), (B.LBM_FP64, 2 | 8), (B.LBM_FP32_STATE, 1 | 8)])
+def test_persistent_grid_equals_one_wave_per_strip(prec, lims):
+    """A persistent grid (1 or 2 workgroups per compute unit, each wave
+    looping over several strips) gives the state of the one-wave-per-strip
+    launch bit for bit, eagerly and from a captured graph, on a 1000 x 700
+    grid cut into 4-row strips (16 x 175 strips, several per wave)."""
+    u0 = np.ascontiguousarray(cases.riemann4(1000, seed=12)[:, :700, :])
+    kw = dict(precision=prec, limiters=lims, bc_x=1, bc_y=1)
+    a = Solver(u0, **kw)
+    a.set_launch(strip_rows=4, waves_per_group=1)
+    a.step(30)
+    ref = a.get_state().cpu().numpy()
+    a.close()
+    for gpc, waves in [(1, 1), (2, 4)]:
+        b = Solver(u0, **kw)
+        b.set_launch(strip_rows=4, waves_per_group=waves, groups_per_cu=gpc)
+        assert b.launch() == (4, waves, gpc)
+        groups = B.lbm_get_grid(b.ctx)[1]
+        assert groups % 8 == 0 and groups * waves < 16 * 175
+        b.step(13)
+        b.step_graph(17)
+        assert np.array_equal(ref, b.get_state().cpu().numpy()), (gpc, waves)
+        b.close()
+
+
+def test_persistent_grid_batch():
+    """An uneven ensemble under a persistent grid (waves striding across
+    instances) equals its one-wave-per-strip run instance by instance."""
+    u0s = [cases.riemann4(s, rng=np.random.default_rng([5, i]))
+           for i, s in enumerate([128, 640, 256, 384, 1024, 128])]
+    kw = dict(precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
+    a = BatchSolver(u0s, **kw)
+    b = BatchSolver(u0s, **kw)
+    a.set_launch(strip_rows=8, waves_per_group=2)
+    b.set_launch(strip_rows=8, waves_per_group=2, groups_per_cu=1)
+    a.step(20)
+    b.step_graph(20)
+    for i in range(len(u0s)):
+        assert np.array_equal(a.moments(i).cpu().numpy(), b.moments(i).cpu().numpy()), i
+    a.close()
+    b.close()
+
+
 def test_error_statuses(gpu):
     n = 32
     u0 = cases.riemann4(n, seed=1)
@@ -353,4 +402,16 @@ def test_error_statuses(gpu):
     assert s.diagnostics()["bouchut"] == 1
     _, st = s.moments(check=False)
     assert st in (B.LBM_EBOUCHUT, B.LBM_EPOSITIVITY, B.LBM_EGUARD)
+    s.close()
+    # launch shapes outside their ranges
+    s = Solver(u0)
+    for bad_launch in [dict(strip_rows=2), dict(strip_rows=8192), dict(waves_per_group=5)]:
+        with pytest.raises(B.LbmError) as e:
+            s.set_launch(**bad_launch)
+        assert e.value.status == B.LBM_EINVAL
+    for bad_grid in (-1, 33):
+        with pytest.raises(B.LbmError) as e:
+            B.lbm_set_grid(s.ctx, bad_grid)
+        assert e.value.status == B.LBM_EINVAL
+    assert s.launch()[2] == 0
     s.close()
