@@ -73,7 +73,7 @@ typedef enum {
                             theta solve and the wavespeed reduction in float64 */
 
 typedef struct {
-  int32_t nx, ny;     /* cells; 1 <= nx, ny <= 2^30 and nx * ny < 2^32 per instance
+  int32_t nx, ny;     /* cells; 1 <= nx, ny < 2^30 and nx * ny < 2^32 per instance
                          (LBM_EINVAL otherwise; the adjoint also needs ny <= 65535) */
   double dx;          /* square cells; cell centres at (i + 1/2) dx */
   double gamma;       /* ideal-gas ratio, > 1 */

@@ -35,11 +35,12 @@ long long strips_x(int nx) { return (nx + 63) / 64; }
 long long strips_y(int ny, int h) { return (ny + h - 1) / h; }
 
 // Grid sizes the kernels address: cells of one instance are indexed with
-// 32-bit row * nx + column offsets, and the edge lanes step two columns past
-// a strip, so each side stays within 2^30 and an instance below 2^32 cells.
+// 32-bit row * nx + column offsets, the edge lanes step two columns past a
+// strip, and a float32 row's size in bytes is a 32-bit buffer extent, so each
+// side stays below 2^30 and an instance below 2^32 cells.
 const char* check_shape(int32_t nx, int32_t ny) {
   if (nx < 1 || ny < 1) return "nx and ny must be >= 1";
-  if (nx > (1 << 30) || ny > (1 << 30)) return "nx and ny must be <= 2^30";
+  if (nx >= (1 << 30) || ny >= (1 << 30)) return "nx and ny must be < 2^30";
   if ((long long)nx * ny > 0xFFFFFFFFll) return "an instance must have fewer than 2^32 cells";
   return nullptr;
 }

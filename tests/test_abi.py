@@ -49,12 +49,13 @@ def test_host_side_validation():
 
 def test_grid_size_limits():
     """Shapes the kernels cannot address are refused before any device work:
-    sides above 2^30 and instances of 2^32 cells or more (32-bit cell
+    sides of 2^30 or more and instances of 2^32 cells or more (32-bit cell
     offsets); the largest admissible shapes are accepted."""
     B.lib()
     ok = B.make_params(65536, 65535)  # 2^32 - 65536 cells
     assert B.lbm_workspace_bytes(ok) > 0
-    for nx, ny in ((65536, 65536), (70000, 70000), ((1 << 30) + 1, 1), (1, (1 << 30) + 1),
+    assert B.lbm_workspace_bytes(B.make_params((1 << 30) - 1, 1)) > 0
+    for nx, ny in ((65536, 65536), (70000, 70000), (1 << 30, 1), (1, 1 << 30), ((1 << 30) + 1, 1),
                    (0, 5), (5, 0)):
         assert B.lbm_workspace_bytes(B.make_params(nx, ny)) == 0, (nx, ny)
     p = B.make_params(128, 128)

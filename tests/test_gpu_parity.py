@@ -134,6 +134,31 @@ def test_theta_and_state_bitwise(case, gpu):
     s.close()
 
 
+@pytest.mark.parametrize("case", THETA_CASES, ids=lambda c: "x".join(map(str, c[:2])) + "-l%d-o%d-bc%d%d-s%d" % c[2:7])
+def test_fp32_state_step_shapes(case, gpu):
+    """One step of the float32-state form from the oracle's state (rounded to
+    float32) against the oracle's float64 step from the same rounded state,
+    on every plane of the new state, over the shapes, limiter sets and
+    boundaries above (ragged strips, columns past the grid's edge, tiny
+    grids): only float32 rounding separates them."""
+    nx, ny, lims, order, bcx, bcy, sponge, ev, kind = case
+    print("fp32 case", case, flush=True)
+    u0 = _u0(kind, nx, ny)
+    ocfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / max(nx, ny), limiters=lims, order=order,
+                         bc_x=bcx, bc_y=bcy, sponge=sponge)
+    S, _ = oracle.init(ocfg, u0)
+    S, _, _, _ = oracle.run(ocfg, S, ev)
+    S32 = S.astype(np.float32)
+    S1, _, _, _ = oracle.step(ocfg, S32.astype(np.float64))
+    s = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
+    s.set_state(gpu.from_numpy(S32).cuda())
+    s.step(1)
+    G = s.get_state().cpu().numpy().astype(np.float64)
+    s.close()
+    err = np.abs(G - S1).max() / np.abs(S1).max()
+    assert err <= 2e-5, "max abs err %.3e relative to the state's largest value" % err
+
+
 def test_table1_on_gpu():
     """Section 4.1 at dx = 1/20 (PP and LMP, fixed a = 10.7, 214 steps): the
     GPU reproduces the oracle bit for bit and hence Table 1's digits."""
