@@ -133,13 +133,21 @@ constexpr double kFastMargin = 1.0 + 0x1p-30;
 // bring a value above 1 + 2^-32 below 1).  In that case min(1, ...) over those
 // two limiters is exactly 1 and the four divisions are skipped; every other
 // lane evaluates the formulas in full, so the result is bit-identical.
-template <class C>
+//
+// LIMS != 0 fixes the limiter set at compile time (the launcher selects such
+// a kernel only for the second-order scheme without sponge layers and with
+// eps <= 1e-12), which folds the limiter tests away; LIMS = 0 reads the set
+// from the scheme.
+template <int LIMS, class C>
 __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], const C dF[4],
                                              double kappa, C muL, C nuL, C muR, C nuR,
                                              int& guard) {
   guard = 0;
-  if (s.order == 1) return 0.0;
-  if (s.limiters == 0) return 1.0;
+  const unsigned lims = LIMS ? (unsigned)LIMS : (unsigned)s.limiters;
+  if (LIMS == 0) {
+    if (s.order == 1) return 0.0;
+    if (s.limiters == 0) return 1.0;
+  }
   const double r0 = us[0], m1 = us[1], m2 = us[2], E = us[3];
   const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
   if (!(r0 > 0.0) || !(g0 < 0.0)) {
@@ -147,16 +155,16 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
     return 0.0;
   }
   const double D = dF[0];
-  const bool fast_ok = s.eps <= 1e-12;
+  const bool fast_ok = LIMS != 0 || s.eps <= 1e-12;  // the launcher checks eps for LIMS != 0
   const bool fast_rho = fast_ok && (D == 0.0 || kappa * r0 >= fabs(D) * kFastMargin);
   double t = 1.0;
-  if ((s.limiters & 1u) && !fast_rho) t = vmin(t, theta_rho_pp(r0, D, kappa, s.eps));
-  if (s.limiters & 2u)
+  if ((lims & 1u) && !fast_rho) t = vmin(t, theta_rho_pp(r0, D, kappa, s.eps));
+  if (lims & 2u)
     t = vmin(t, theta_rho_lmp(r0, D, kappa, (double)muL, (double)nuL, (double)muR, (double)nuR));
-  if (s.limiters & 4u)
+  if (lims & 4u)
     t = vmin(t, theta_rho_lmp(r0, D, kappa, s.rlmp_lo * (double)muL, s.rlmp_hi * (double)nuL,
                               s.rlmp_lo * (double)muR, s.rlmp_hi * (double)nuR));
-  if (s.limiters & 8u) {
+  if (lims & 8u) {
     const double Dm1 = dF[1], Dm2 = dF[2], DE = dF[3];
     const double g1 = 2.0 * (D * E + DE * r0 - Dm1 * m1 - Dm2 * m2);
     const double g2 = Dm1 * Dm1 + Dm2 * Dm2 - 2.0 * D * DE;
@@ -305,7 +313,7 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
 // face evaluation per row).  The strip to the west evaluates that same face
 // with the same inputs and code, so both cells of a strip-edge face see the
 // same theta.
-template <class T, class C>
+template <class T, class C, int LIMS>
 __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                             int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -320,7 +328,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   const int hslot = first ? 4 : 8;
   const int y0 = ys * A.strip_h;
   const int y1 = min(y0 + A.strip_h, ny);
-  const bool sponge = sc.sponge > 0;
+  const bool sponge = LIMS == 0 && sc.sponge > 0;
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
@@ -424,9 +432,9 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     }
     int gx, gy, gw;
     const C zero = C(0);
-    double thx = face_theta(sc, usx, dF, K.klim, zero, zero, zero, zero, gx);
-    double thy = face_theta(sc, usy, dG, K.klim, zero, zero, zero, zero, gy);
-    double th_edge = face_theta(sc, usw, dFw, K.klim, zero, zero, zero, zero, gw);
+    double thx = face_theta<LIMS>(sc, usx, dF, K.klim, zero, zero, zero, zero, gx);
+    double thy = face_theta<LIMS>(sc, usy, dG, K.klim, zero, zero, zero, zero, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.klim, zero, zero, zero, zero, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
@@ -448,7 +456,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       n_guard += gw;
       n_lim += (th_edge < 1.0);
     }
-    if (A.theta_x) {
+    if (LIMS == 0 && A.theta_x) {
       if (row0 && first) A.theta_x[(long long)L * (nx + 1) + x0] = th_edge;
       if (row0 && gi + 1 <= nx) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row0 || row1) && L >= 0 && L <= ny) A.theta_y[(long long)L * nx + gi] = thy;
@@ -537,7 +545,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
 // rho, m_1 of x0 + 65.  From them each evaluates the bounds of its halo cell,
 // and lane 0 the west edge face x0 - 1/2, with the same expressions as every
 // other lane, so both strips beside an edge face see the same theta.
-template <class T, class C>
+template <class T, class C, int LIMS>
 __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                           int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -552,7 +560,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   const int hslot = first ? 4 : 8;
   const int y0 = ys * A.strip_h;
   const int y1 = min(y0 + A.strip_h, ny);
-  const bool sponge = sc.sponge > 0;
+  const bool sponge = LIMS == 0 && sc.sponge > 0;
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
@@ -731,9 +739,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
     const C muE = from_right_or(mu1, hmu);
     const C nuE = from_right_or(nu1, hnu);
     int gx, gy, gw;
-    double thx = face_theta(sc, pusx, pdF, K.klim, mu1, nu1, muE, nuE, gx);
-    double thy = face_theta(sc, pusy, pdG, K.klim, pmu, pnu, mu1, nu1, gy);
-    double th_edge = face_theta(sc, usw, dFw, K.klim, hmu, hnu, mu1, nu1, gw);
+    double thx = face_theta<LIMS>(sc, pusx, pdF, K.klim, mu1, nu1, muE, nuE, gx);
+    double thy = face_theta<LIMS>(sc, pusy, pdG, K.klim, pmu, pnu, mu1, nu1, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.klim, hmu, hnu, mu1, nu1, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi + 1, L - 1, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 2, nx, ny) || in_sponge(sc, gi, L - 1, nx, ny)) thy = 0.0;
@@ -755,7 +763,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       n_guard += gw;
       n_lim += (th_edge < 1.0);
     }
-    if (A.theta_x) {
+    if (LIMS == 0 && A.theta_x) {
       if (row1 && first) A.theta_x[(long long)(L - 1) * (nx + 1) + x0] = th_edge;
       if (row1 && gi + 1 <= nx) A.theta_x[(long long)(L - 1) * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row1 || row2) && L - 1 >= 0 && L - 1 <= ny)
@@ -866,7 +874,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp);
 }
 
-template <class T, class C, bool LMP, int WPE>
+template <class T, class C, bool LMP, int WPE, int LIMS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
@@ -894,9 +902,9 @@ void step_kernel(StepArgs A) {
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
     if (LMP)
-      march_lmp<T, C>(A, in, A.slots + ii, xs, ys, lane);
+      march_lmp<T, C, LIMS>(A, in, A.slots + ii, xs, ys, lane);
     else
-      march_short<T, C>(A, in, A.slots + ii, xs, ys, lane);
+      march_short<T, C, LIMS>(A, in, A.slots + ii, xs, ys, lane);
   }
 }
 
@@ -1067,20 +1075,35 @@ int grid_for_reduce(long long n) { return grid_for(n, 1024); }
 
 }  // namespace
 
+// Step launch.  The benchmarked limiter sets (PP + pressure; PP + LMP +
+// pressure) of the second-order scheme without sponge layers or face output
+// run kernels with the set fixed at compile time (same results; A/B on one
+// box: 2% faster in float64 and on the ensembles, 4% on the LMP runs); all
+// other configurations run the general kernels.
+template <class T, bool LMP, int WPE>
+static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
+  constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
+  if (lims == kFixed)
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0>), grid, block, 0, s, a);
+}
+
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
+  const int lims = (a.sc.order == 2 && a.sc.sponge == 0 && a.sc.eps <= 1e-12 && !a.theta_x) ? a.sc.limiters : 0;
   const dim3 block(64 * a.waves_per_group);
   const dim3 grid(a.groups);
   if (precision == 0) {
     if (lmp)
-      hipLaunchKernelGGL((step_kernel<double, double, true, VLBM_WPE_F64_LMP>), grid, block, 0, s, a);
+      launch_step_as<double, true, VLBM_WPE_F64_LMP>(a, lims, grid, block, s);
     else
-      hipLaunchKernelGGL((step_kernel<double, double, false, VLBM_WPE_F64>), grid, block, 0, s, a);
+      launch_step_as<double, false, VLBM_WPE_F64>(a, lims, grid, block, s);
   } else {
     if (lmp)
-      hipLaunchKernelGGL((step_kernel<float, float, true, VLBM_WPE_F32_LMP>), grid, block, 0, s, a);
+      launch_step_as<float, true, VLBM_WPE_F32_LMP>(a, lims, grid, block, s);
     else
-      hipLaunchKernelGGL((step_kernel<float, float, false, VLBM_WPE_F32>), grid, block, 0, s, a);
+      launch_step_as<float, false, VLBM_WPE_F32>(a, lims, grid, block, s);
   }
   return hipGetLastError();
 }
