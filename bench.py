@@ -396,7 +396,7 @@ def bench_batch(a):
                        "fp32 state, PP + pressure, outflow, a = 4.4 lambda, hipGraph replay",
            "instances": 256, "cells": cells},
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": None}, status=int(st),
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("batch256_fp32", launch)}, status=int(st),
           launch=list(launch), per_class=per_class,
           **({} if a.no_cpu else {"cpu_baseline": cpu_batch(sides, u0s)}))
 
