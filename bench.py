@@ -129,7 +129,8 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     achieved = BYTES_PER_CELL[form] * cells / (avg_ms * 1e-3) / 1e9
     return {
         "value": glups, "ms_per_step": avg_ms, "wall_s": wall, "status": int(st),
-        "launch": {"strip_rows": launch[0], "waves_per_group": launch[1], "groups_per_cu": launch[2]},
+        "launch": {"strip_rows": launch[0], "waves_per_group": launch[1], "groups_per_cu": launch[2],
+                   "strip_mode": launch[3]},
         "diag": {"t": d["t"], "lambda": d["lam"], "n_bad": d["n_bad"], "n_guard": d["n_guard"]},
         "conservation_drift": drift,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -190,7 +191,7 @@ def traffic_for(key, launch):
     """Measured HBM bytes per launch (rocprofv3 counters) of the workload and
     form `key` (e.g. "blast8192_fp32"), if recorded for the current kernel
     source and the same launch shape (strip rows, waves per group, groups per
-    CU): the re-read halo rows depend on the strip height."""
+    CU, strip mode): the re-read halo rows depend on the strip height."""
     try:
         with open(PMC_FILE) as f:
             rec = json.load(f)
@@ -200,7 +201,11 @@ def traffic_for(key, launch):
     entry = rec.get(key)
     if not entry or entry.get("source_sha256") != kernel_source_digest() or not os.path.exists(lib):
         return None
-    if list(entry.get("launch", [])) != list(launch):
+    def pad(x):  # (strip rows, waves, groups per CU, strip mode); missing values are 0
+        x = list(x)
+        return x + [0] * (4 - len(x))
+
+    if "launch" not in entry or pad(entry["launch"]) != pad(launch):
         return None
     return entry.get("bytes_per_launch")
 
@@ -476,7 +481,7 @@ def main():
         forms[form], rho[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
         L = forms[form]["launch"]
         forms[form]["roofline"]["traffic"] = traffic_for(
-            "blast%d_%s" % (a.n, form), [L["strip_rows"], L["waves_per_group"], L["groups_per_cu"]])
+            "blast%d_%s" % (a.n, form), [L["strip_rows"], L["waves_per_group"], L["groups_per_cu"], L["strip_mode"]])
         print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
             form, forms[form]["value"], forms[form]["ms_per_step"],
             100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)

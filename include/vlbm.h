@@ -218,14 +218,14 @@ lbm_status lbm_step_adjoint_theta(lbm_ctx* ctx, const double* U_n_dev,
 lbm_status lbm_init_adjoint(lbm_ctx* ctx, const double* u0_dev,
                             const double* Ubar0_dev, double* u0bar_dev);
 
-/* Times the step kernel for the candidate strip heights, waves per workgroup
- * and grids (one wave per strip, or a persistent grid of 1, 2 or 4
- * workgroups per compute unit) on the context's own problem and keeps the
- * fastest: a first pass times every candidate, then the four fastest are
- * timed again, best of three.  The choice is recorded in a JSON cache file
- * keyed by problem shape (NULL path = no file) as [rows, waves, groups per
- * CU]; a cached entry is used without timing (an entry of two values has no
- * persistent grid).  The timed launches read the current state and write the
+/* Times the step kernel for the candidate strip heights, waves per workgroup,
+ * grids (one wave per strip, or a persistent grid of 1, 2 or 4 workgroups
+ * per compute unit) and, for ensembles, both strip modes on the context's own
+ * problem and keeps the fastest: a first pass times every candidate, then the
+ * four fastest are timed again, best of three.  The choice is recorded in a
+ * JSON cache file keyed by problem shape (NULL path = no file) as [rows,
+ * waves, groups per CU, strip mode]; a cached entry is used without timing
+ * (missing trailing values are 0).  The timed launches read the current state and write the
  * other buffer, and the slots (lambda, t, counters) are restored, so the
  * context's state and step count are unchanged.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
@@ -238,6 +238,15 @@ lbm_status lbm_autotune(lbm_ctx* ctx, const char* cache_json_path);
  * the shape drops captured graphs. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t strip_rows, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* waves_per_group);
+
+/* Strip heights of an ensemble.  Mode 0 (the default): every instance uses
+ * the strip height of lbm_set_launch.  Mode 1: each instance uses the
+ * tallest power of two that exceeds neither that height nor a quarter of its
+ * own rows (at least 4), and the instances with the tallest strips are
+ * dispatched first.  Results do not depend on the mode.  LBM_EINVAL for other
+ * values; changing the mode drops captured graphs. */
+lbm_status lbm_set_strip_mode(lbm_ctx* ctx, int32_t mode);
+lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
 
 /* Grid of the step kernel.  groups_per_cu = 0 (the default) launches one wave
  * per strip; k in [1, 32] launches a persistent grid of at most k workgroups

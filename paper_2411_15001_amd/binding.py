@@ -38,7 +38,7 @@ EXPORTS = [
     "lbm_step", "lbm_step_graph", "lbm_step_theta", "lbm_moments", "lbm_diagnostics",
     "lbm_totals",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_adjoint",
-    "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch", "lbm_set_grid", "lbm_get_grid",
+    "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch", "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -109,6 +109,8 @@ def lib():
         L.lbm_set_launch.argtypes = [vp, i32, i32]
         L.lbm_get_launch.argtypes = [vp, i32p, i32p]
         L.lbm_set_grid.argtypes = [vp, i32]
+        L.lbm_set_strip_mode.argtypes = [vp, i32]
+        L.lbm_get_strip_mode.argtypes = [vp, i32p]
         L.lbm_get_grid.argtypes = [vp, i32p, i32p]
         L.lbm_status_string.argtypes = [ctypes.c_int]
         L.lbm_status_string.restype = ctypes.c_char_p
@@ -348,6 +350,16 @@ def lbm_get_launch(ctx):
 
 def lbm_set_grid(ctx, groups_per_cu=0):
     return _check(lib().lbm_set_grid(ctx, int(groups_per_cu)), ctx)
+
+
+def lbm_set_strip_mode(ctx, mode=0):
+    return _check(lib().lbm_set_strip_mode(ctx, int(mode)), ctx)
+
+
+def lbm_get_strip_mode(ctx):
+    m = ctypes.c_int32()
+    _check(lib().lbm_get_strip_mode(ctx, ctypes.byref(m)), ctx)
+    return m.value
 
 
 def lbm_get_grid(ctx):

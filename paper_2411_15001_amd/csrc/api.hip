@@ -143,6 +143,7 @@ struct lbm_ctx {
   hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
   long long step = 0;
   int strip_rows = 64;
+  int strip_mode = 0;  // 0: every instance strip_rows; 1: matched to the instance's height
   int waves = 4;
   int xcd = 1;
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
@@ -170,14 +171,42 @@ lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
   return fail(c, LBM_EDEVICE, m);
 }
 
-// Rebuild the strip tables after a change of strip height.
+// Rows per strip of an instance of ny rows.  Mode 0: the context's strip
+// height.  Mode 1 (ensembles of uneven sizes): the tallest power of two that
+// neither exceeds the strip height nor a quarter of the instance's rows (at
+// least kMinStripRows), so that small instances are cut into more, shorter
+// strips while large ones keep tall strips and few re-read halo rows.
+int inst_strip_rows(const lbm_ctx* c, int ny) {
+  if (c->strip_mode == 0) return c->strip_rows;
+  int h = kMinStripRows;
+  while (h * 2 <= c->strip_rows && h * 2 <= ny / 4) h *= 2;
+  return h;
+}
+
+// Rebuild the strip tables after a change of strip height.  Each instance's
+// strips are consecutive work items; in mode 1 the instances with the tallest
+// strips (and, among equal heights, the most rows) come first, so that the
+// longest waves are dispatched first and the short ones fill the end of the
+// launch.
 void build_items(lbm_ctx* c) {
+  std::vector<int> order(c->n_inst);
+  for (int i = 0; i < c->n_inst; ++i) {
+    order[i] = i;
+    Inst& in = c->insts[i];
+    in.strip_h = inst_strip_rows(c, in.ny);
+    in.xs = (int)strips_x(in.nx);
+    in.ys = (int)strips_y(in.ny, in.strip_h);
+  }
+  if (c->strip_mode == 1)
+    std::stable_sort(order.begin(), order.end(), [c](int a, int b) {
+      const Inst &x = c->insts[a], &y = c->insts[b];
+      if (x.strip_h != y.strip_h) return x.strip_h > y.strip_h;
+      return x.ny > y.ny;
+    });
   c->n_items = 0;
   c->item_inst.clear();
-  for (int i = 0; i < c->n_inst; ++i) {
+  for (int i : order) {
     Inst& in = c->insts[i];
-    in.xs = (int)strips_x(in.nx);
-    in.ys = (int)strips_y(in.ny, c->strip_rows);
     in.item0 = c->n_items;
     const long long k = (long long)in.xs * in.ys;
     if (c->n_inst > 1)
@@ -214,6 +243,15 @@ lbm_status upload_tables(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// New strip tables for the current strip height and mode; captured graphs,
+// which hold the old launch, are dropped.
+lbm_status rebuild_launch(lbm_ctx* c) {
+  build_items(c);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return upload_tables(c);
+}
+
 // Workgroups of a step launch.  By default one wave per strip, for single
 // instances and ensembles alike; with grid_per_cu = k > 0 a persistent grid
 // of k workgroups per compute unit whose waves stride over the strips (the
@@ -240,7 +278,6 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
   a.n_items = c->n_items;
   a.n_inst = c->n_inst;
   a.slot = slot;
-  a.strip_h = c->strip_rows;
   a.waves_per_group = c->waves;
   a.xcd_remap = c->xcd;
   a.groups = compute_groups(c);
@@ -617,10 +654,20 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t rows, int32_t waves) {
   if (waves != 0 && (waves < 1 || waves > 4)) return fail(c, LBM_EINVAL, "waves per group must lie in [1, 4]");
   if (rows) c->strip_rows = rows;
   if (waves) c->waves = waves;
-  build_items(c);
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
-  return upload_tables(c);
+  return rebuild_launch(c);
+}
+
+lbm_status lbm_set_strip_mode(lbm_ctx* c, int32_t mode) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (mode != 0 && mode != 1) return fail(c, LBM_EINVAL, "strip mode must be 0 or 1");
+  c->strip_mode = mode;
+  return rebuild_launch(c);
+}
+
+lbm_status lbm_get_strip_mode(const lbm_ctx* c, int32_t* mode) {
+  if (!c || !mode) return LBM_EINVAL;
+  *mode = c->strip_mode;
+  return LBM_OK;
 }
 
 lbm_status lbm_get_launch(const lbm_ctx* c, int32_t* rows, int32_t* waves) {
@@ -653,8 +700,8 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   long long cells = c->plane;
   snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d", c->n_inst, c->insts[0].nx,
            c->insts[0].ny, cells, c->p.precision, c->p.limiters, c->p.order);
-  // cache lookup: a flat JSON object {"key": [rows, waves, groups per CU], ...}
-  // (entries of two values have no persistent grid)
+  // cache lookup: a flat JSON object {"key": [rows, waves, groups per CU,
+  // strip mode], ...} (missing trailing values are 0)
   std::string text;
   if (path) {
     FILE* f = fopen(path, "rb");
@@ -666,11 +713,13 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
       const std::string k = std::string("\"") + key + "\"";
       size_t pos = text.find(k);
       if (pos != std::string::npos) {
-        int rows = 0, waves = 0, grid = 0;
-        const int got = sscanf(text.c_str() + pos + k.size(), " : [ %d , %d , %d ]", &rows, &waves, &grid);
+        int rows = 0, waves = 0, grid = 0, mode = 0;
+        const int got = sscanf(text.c_str() + pos + k.size(), " : [ %d , %d , %d , %d ]", &rows, &waves,
+                               &grid, &mode);
         if (got >= 2) {
           lbm_status st = lbm_set_launch(c, rows, waves);
-          if (st == LBM_OK) st = lbm_set_grid(c, got == 3 ? grid : 0);
+          if (st == LBM_OK) st = lbm_set_grid(c, got >= 3 ? grid : 0);
+          if (st == LBM_OK) st = lbm_set_strip_mode(c, got >= 4 ? mode : 0);
           return st;
         }
       }
@@ -682,14 +731,17 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   const int rows_c[] = {4, 8, 16, 32, 64, 128, 256};
   const int waves_c[] = {1, 2, 4};
   const int grid_c[] = {0, 1, 2, 4};  // one wave per strip, or persistent grids
+  const int n_modes = c->n_inst > 1 ? 2 : 1;  // matched strip heights: ensembles only
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, LBM_EDEVICE, "hipEventCreate");
   float best = 1e30f;
-  int best_r = c->strip_rows, best_w = c->waves, best_g = c->grid_per_cu;
-  // average time of one launch of the shape (r, w, gpc); launches all read the
-  // current state and write the other buffer, so the state is not advanced
-  auto time_shape = [&](int r, int w, int gpc, float work_ms, float& ms) -> lbm_status {
+  int best_r = c->strip_rows, best_w = c->waves, best_g = c->grid_per_cu, best_m = c->strip_mode;
+  // average time of one launch of the shape (r, w, gpc, mode); launches all
+  // read the current state and write the other buffer, so the state is not
+  // advanced
+  auto time_shape = [&](int r, int w, int gpc, int mode, float work_ms, float& ms) -> lbm_status {
+    c->strip_mode = mode;
     lbm_status s2 = lbm_set_launch(c, r, w);
     if (s2 == LBM_OK) s2 = lbm_set_grid(c, gpc);
     if (s2 != LBM_OK) return s2;
@@ -721,7 +773,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   // of three (shapes within a few percent of each other are told apart)
   struct Cand {
     float ms;
-    int r, w, g;
+    int r, w, g, m;
   };
   std::vector<Cand> cands;
   auto bail = [&](lbm_status s2) {
@@ -729,14 +781,18 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
     (void)hipEventDestroy(e1);
     return s2;
   };
+  int max_ny = 0;
+  for (const Inst& in : c->insts) max_ny = std::max(max_ny, in.ny);
   for (int r : rows_c) {
-    if (r > 2 * c->insts[0].ny && r != 16) continue;
+    if (r > 2 * max_ny && r != 16) continue;
     for (int w : waves_c) {
       for (int gpc : grid_c) {
-        float ms = -1.0f;
-        st = time_shape(r, w, gpc, 4.0f, ms);
-        if (st != LBM_OK) return bail(st);
-        if (ms >= 0.0f) cands.push_back({ms, r, w, gpc});
+        for (int m = 0; m < n_modes; ++m) {
+          float ms = -1.0f;
+          st = time_shape(r, w, gpc, m, 4.0f, ms);
+          if (st != LBM_OK) return bail(st);
+          if (ms >= 0.0f) cands.push_back({ms, r, w, gpc, m});
+        }
       }
     }
   }
@@ -746,7 +802,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   for (int round = 0; round < 3; ++round) {
     for (Cand& k : cands) {
       float ms = -1.0f;
-      st = time_shape(k.r, k.w, k.g, 12.0f, ms);
+      st = time_shape(k.r, k.w, k.g, k.m, 12.0f, ms);
       if (st != LBM_OK) return bail(st);
       k.ms = std::min(k.ms, ms);
     }
@@ -757,12 +813,14 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
       best_r = k.r;
       best_w = k.w;
       best_g = k.g;
+      best_m = k.m;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   st = write_slots(c, saved);
   if (st != LBM_OK) return st;
+  c->strip_mode = best_m;
   st = lbm_set_launch(c, best_r, best_w);
   if (st == LBM_OK) st = lbm_set_grid(c, best_g);
   if (st != LBM_OK) return st;
@@ -771,7 +829,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
     std::string body = text;
     size_t end = body.rfind('}');
     char entry[256];
-    snprintf(entry, sizeof(entry), "\"%s\": [%d, %d, %d]", key, best_r, best_w, best_g);
+    snprintf(entry, sizeof(entry), "\"%s\": [%d, %d, %d, %d]", key, best_r, best_w, best_g, best_m);
     if (end == std::string::npos) {
       body = std::string("{\n  ") + entry + "\n}\n";
     } else {

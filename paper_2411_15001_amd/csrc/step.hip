@@ -326,8 +326,8 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   // halo column: west of lane 0 (its u and u_1), east of lane 63 (u and u_2)
   const int hcol = first ? map_index(x0 - 1, nx, sc.bc_x) : map_index(x0 + 64, nx, sc.bc_x);
   const int hslot = first ? 4 : 8;
-  const int y0 = ys * A.strip_h;
-  const int y1 = min(y0 + A.strip_h, ny);
+  const int y0 = ys * in.strip_h;
+  const int y1 = min(y0 + in.strip_h, ny);
   const bool sponge = LIMS == 0 && sc.sponge > 0;
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
@@ -558,8 +558,8 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   const int hcol = first ? map_index(x0 - 1, nx, sc.bc_x) : map_index(x0 + 64, nx, sc.bc_x);
   const int ocol = first ? map_index(x0 - 2, nx, sc.bc_x) : map_index(x0 + 65, nx, sc.bc_x);
   const int hslot = first ? 4 : 8;
-  const int y0 = ys * A.strip_h;
-  const int y1 = min(y0 + A.strip_h, ny);
+  const int y0 = ys * in.strip_h;
+  const int y1 = min(y0 + in.strip_h, ny);
   const bool sponge = LIMS == 0 && sc.sponge > 0;
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);

@@ -19,6 +19,8 @@ struct Inst {
   double dx;
   int nx, ny;
   int xs, ys;      // strips along x and y
+  int strip_h;     // rows per strip of this instance
+  int pad_;
 };
 
 // Per-instance device scalars.  lam and t rotate over three slots: step n
@@ -42,7 +44,6 @@ struct StepArgs {
   long long n_items;
   int n_inst;
   int slot;               // step index mod 3
-  int strip_h;            // rows per strip
   int waves_per_group;
   int xcd_remap;          // map consecutive groups onto one XCD
   int groups;             // launched workgroups

@@ -80,14 +80,17 @@ class Solver:
         B.lbm_autotune(self.ctx, cache)
         return self.launch()
 
-    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None):
+    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None, strip_mode=None):
         B.lbm_set_launch(self.ctx, strip_rows, waves_per_group)
         if groups_per_cu is not None:
             B.lbm_set_grid(self.ctx, groups_per_cu)
+        if strip_mode is not None:
+            B.lbm_set_strip_mode(self.ctx, strip_mode)
 
     def launch(self):
-        """(strip rows, waves per workgroup, groups per CU; 0 = one wave per strip)"""
-        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0],)
+        """(strip rows, waves per workgroup, groups per CU (0 = one wave per
+        strip), strip mode (1 = heights matched to each instance))"""
+        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0], B.lbm_get_strip_mode(self.ctx))
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -157,14 +160,17 @@ class BatchSolver:
         B.lbm_autotune(self.ctx, cache)
         return self.launch()
 
-    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None):
+    def set_launch(self, strip_rows=0, waves_per_group=0, groups_per_cu=None, strip_mode=None):
         B.lbm_set_launch(self.ctx, strip_rows, waves_per_group)
         if groups_per_cu is not None:
             B.lbm_set_grid(self.ctx, groups_per_cu)
+        if strip_mode is not None:
+            B.lbm_set_strip_mode(self.ctx, strip_mode)
 
     def launch(self):
-        """(strip rows, waves per workgroup, groups per CU; 0 = one wave per strip)"""
-        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0],)
+        """(strip rows, waves per workgroup, groups per CU (0 = one wave per
+        strip), strip mode (1 = heights matched to each instance))"""
+        return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0], B.lbm_get_strip_mode(self.ctx))
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -86,8 +86,8 @@ def test_batch_autotune_and_cache(tmp_path):
     bs = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
     ref = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
     cache = str(tmp_path / "tune.json")
-    rows, waves, grid = bs.autotune(cache)
-    assert rows >= 4 and 1 <= waves <= 4 and grid in (0, 1, 2, 4)
+    rows, waves, grid, mode = bs.autotune(cache)
+    assert rows >= 4 and 1 <= waves <= 4 and grid in (0, 1, 2, 4) and mode in (0, 1)
     assert open(cache).read().count("[") == 1
     # tuning does not advance the state
     bs.step(10)
@@ -96,7 +96,7 @@ def test_batch_autotune_and_cache(tmp_path):
         assert np.array_equal(bs.moments(i).cpu().numpy(), ref.moments(i).cpu().numpy())
     # a second context reads the cached entry
     again = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
-    assert again.autotune(cache) == (rows, waves, grid)
+    assert again.autotune(cache) == (rows, waves, grid, mode)
     for x in (bs, ref, again):
         x.close()
 

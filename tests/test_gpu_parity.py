@@ -393,7 +393,7 @@ def test_persistent_grid_equals_one_wave_per_strip(prec, lims):
     for gpc, waves in [(1, 1), (2, 4)]:
         b = Solver(u0, **kw)
         b.set_launch(strip_rows=4, waves_per_group=waves, groups_per_cu=gpc)
-        assert b.launch() == (4, waves, gpc)
+        assert b.launch() == (4, waves, gpc, 0)
         groups = B.lbm_get_grid(b.ctx)[1]
         assert groups % 8 == 0 and groups * waves < 16 * 175
         b.step(13)
@@ -418,6 +418,34 @@ def test_persistent_grid_batch():
         assert np.array_equal(a.moments(i).cpu().numpy(), b.moments(i).cpu().numpy()), i
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec,lims", [(B.LBM_FP32_STATE, 1 | 8), (B.LBM_FP64, 1 | 2 | 8)])
+def test_strip_mode_batch(prec, lims):
+    """Strip heights matched to each instance (mode 1: 32 rows for the small
+    and ragged instances, 64 for the others, largest first) give every
+    instance of an uneven ensemble the state of the uniform 64-row launch bit
+    for bit, eagerly, from a graph and under a persistent grid."""
+    sides = [(128, 128), (640, 640), (256, 256), (136, 200), (1024, 1024), (200, 72), (384, 384)]
+    u0s = [np.ascontiguousarray(cases.riemann4(max(nx, ny), rng=np.random.default_rng([9, i]))[:, :ny, :nx])
+           for i, (nx, ny) in enumerate(sides)]
+    kw = dict(precision=prec, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1)
+    a = BatchSolver(u0s, **kw)
+    a.set_launch(strip_rows=64, waves_per_group=2)
+    a.step(12)
+    for gpc in (0, 1):
+        b = BatchSolver(u0s, **kw)
+        b.set_launch(strip_rows=64, waves_per_group=2, groups_per_cu=gpc, strip_mode=1)
+        assert b.launch() == (64, 2, gpc, 1)
+        b.step(5)
+        b.step_graph(7)
+        for i in range(len(sides)):
+            assert np.array_equal(a.moments(i).cpu().numpy(), b.moments(i).cpu().numpy()), (gpc, i)
+        b.close()
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_set_strip_mode(a.ctx, 2)
+    assert e.value.status == B.LBM_EINVAL
+    a.close()
 
 
 def test_error_statuses(gpu):
