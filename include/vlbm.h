@@ -163,6 +163,22 @@ lbm_status lbm_step_graph(lbm_ctx* ctx, int32_t nsteps);
  * instance only. */
 lbm_status lbm_step_theta(lbm_ctx* ctx, double* theta_x_dev, double* theta_y_dev);
 
+/* One step of the context whose state is read from src_dev and written to
+ * dst_dev, caller buffers of lbm_state_bytes in the state layout, instead of
+ * the context's own buffers; theta_x_dev / theta_y_dev as in lbm_step_theta
+ * (both NULL: no face output).  The step count, lambda, t and counters
+ * advance as for lbm_step, so src_dev must hold the state the context is at:
+ * its own current buffer (after lbm_init, lbm_step or lbm_set_state) or the
+ * dst_dev of the previous lbm_step_between.  Afterwards the context's current
+ * state lives in dst_dev: lbm_step, lbm_step_graph, lbm_step_theta,
+ * lbm_moments, lbm_totals, lbm_get_state and lbm_autotune return LBM_EINVAL
+ * until lbm_set_state loads a state again.  For recomputing a segment of a
+ * rollout step by step without copying each state out.  Single instance;
+ * LBM_EINVAL if src and dst overlap or dst is the context's current buffer.
+ * Asynchronous. */
+lbm_status lbm_step_between(lbm_ctx* ctx, const void* src_dev, void* dst_dev,
+                            double* theta_x_dev, double* theta_y_dev);
+
 /* Moments (rho, m1, m2, E) of instance `inst` as float64 [4][ny][nx] into
  * u_out_dev.  Synchronises the stream; returns the first device event counted
  * since the last synchronising call (LBM_EPOSITIVITY, LBM_EGUARD,

@@ -9,7 +9,8 @@ and theta = 1 everywhere this is the exact derivative of the map).
 
 Memory: the forward pass keeps one state every `checkpoint_every` steps;
 the backward pass restores each checkpoint and recomputes its segment with
-lbm_step_theta, keeping each step's input state and face factors theta, then
+lbm_step_between, each step writing its output state into the buffer that
+the next step reads and keeping its face factors theta (no state copies), then
 runs the adjoint kernel step by step in reverse with those factors
 (lbm_step_adjoint_theta; the same theta that lbm_step_adjoint would
 recompute), and finally maps the result back through the initialisation
@@ -53,18 +54,22 @@ class _Rollout(torch.autograd.Function):
         ubar = torch.zeros((20, ny, nx), dtype=torch.float64, device=u0.device)
         ubar[0:4] = grad_out.to(torch.float64)
         spare = torch.empty_like(ubar)
+        last = torch.empty_like(ckpts[0])  # the output of a segment's last step
         for seg in range(len(ckpts) - 1, -1, -1):
             n = min(k, nsteps - seg * k)
             # recompute the segment from its checkpoint: each step's input
-            # state and its face factors
+            # state and its face factors; every step writes its output straight
+            # into the buffer that holds the next step's input
             s.set_state(ckpts[seg])
-            states, thetas = [], []
-            for _ in range(n):
-                states.append(s.get_state())
+            states, thetas = [ckpts[seg]], []
+            for i in range(n):
+                dst = last if i == n - 1 else torch.empty_like(ckpts[0])
                 tx = torch.empty((ny, nx + 1), dtype=torch.float64, device=u0.device)
                 ty = torch.empty((ny + 1, nx), dtype=torch.float64, device=u0.device)
-                B.lbm_step_theta(s.ctx, tx, ty)
+                B.lbm_step_between(s.ctx, states[-1], dst, tx, ty)
                 thetas.append((tx, ty))
+                if i < n - 1:
+                    states.append(dst)
             for st, (tx, ty) in zip(reversed(states), reversed(thetas)):
                 B.lbm_step_adjoint_theta(s.ctx, st, tx, ty, ubar, spare)
                 ubar, spare = spare, ubar

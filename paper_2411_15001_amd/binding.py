@@ -37,8 +37,9 @@ EXPORTS = [
     "lbm_workspace_bytes", "lbm_batch_workspace_bytes", "lbm_init", "lbm_init_batch",
     "lbm_step", "lbm_step_graph", "lbm_step_theta", "lbm_moments", "lbm_diagnostics",
     "lbm_totals",
-    "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_adjoint",
-    "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch", "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode",
+    "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_between", "lbm_step_adjoint",
+    "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
+    "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -104,6 +105,7 @@ def lib():
         L.lbm_set_state.argtypes = [vp, vp]
         L.lbm_step_adjoint.argtypes = [vp, vp, vp, vp]
         L.lbm_step_adjoint_theta.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lbm_step_between.argtypes = [vp, vp, vp, vp, vp]
         L.lbm_init_adjoint.argtypes = [vp, vp, vp, vp]
         L.lbm_autotune.argtypes = [vp, ctypes.c_char_p]
         L.lbm_set_launch.argtypes = [vp, i32, i32]
@@ -251,6 +253,26 @@ def lbm_step_theta(ctx, theta_x, theta_y):
     _require_cuda(theta_x, torch.float64, ny * (nx + 1), "theta_x")
     _require_cuda(theta_y, torch.float64, (ny + 1) * nx, "theta_y")
     return _check(lib().lbm_step_theta(ctx, _ptr(theta_x), _ptr(theta_y)), ctx)
+
+
+def lbm_step_between(ctx, src, dst, theta_x=None, theta_y=None):
+    """One step from the state in src to dst (caller buffers); see the C
+    declaration for the context's state afterwards."""
+    import torch
+
+    _require_cuda(src)
+    _require_state_bytes(ctx, src)
+    _require_cuda(dst)
+    _require_state_bytes(ctx, dst)
+    if (theta_x is None) != (theta_y is None):
+        raise ValueError("give both theta buffers or neither")
+    tx = ty = None
+    if theta_x is not None:
+        nx, ny = _inst_shape(ctx)
+        _require_cuda(theta_x, torch.float64, ny * (nx + 1), "theta_x")
+        _require_cuda(theta_y, torch.float64, (ny + 1) * nx, "theta_y")
+        tx, ty = _ptr(theta_x), _ptr(theta_y)
+    return _check(lib().lbm_step_between(ctx, _ptr(src), _ptr(dst), tx, ty), ctx)
 
 
 def lbm_moments(ctx, inst, out, check=True):

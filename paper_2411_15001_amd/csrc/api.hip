@@ -148,6 +148,7 @@ struct lbm_ctx {
   int xcd = 1;
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
   int n_cu = 256;       // compute units of the context's device
+  bool detached = false;  // the current state lives in a caller buffer (lbm_step_between)
   std::string err;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
 
@@ -181,6 +182,14 @@ int inst_strip_rows(const lbm_ctx* c, int ny) {
   int h = kMinStripRows;
   while (h * 2 <= c->strip_rows && h * 2 <= ny / 4) h *= 2;
   return h;
+}
+
+// After lbm_step_between the context's own buffer no longer holds its
+// current state: calls that read it fail until lbm_set_state.
+lbm_status require_attached(lbm_ctx* c) {
+  if (c->detached)
+    return fail(c, LBM_EINVAL, "the current state is in a caller buffer (lbm_step_between); call lbm_set_state first");
+  return LBM_OK;
 }
 
 // Rebuild the strip tables after a change of strip height.  Each instance's
@@ -286,6 +295,7 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
 }
 
 lbm_status launch_one(lbm_ctx* c) {
+  if (lbm_status st = require_attached(c)) return st;
   vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
   hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
@@ -511,6 +521,7 @@ lbm_status lbm_step_theta(lbm_ctx* c, double* tx, double* ty) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1) return fail(c, LBM_ENOTSUP, "face output is single-instance only");
   if (!tx || !ty) return fail(c, LBM_EINVAL, "theta buffers must be device pointers");
+  if (lbm_status st = require_attached(c)) return st;
   vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
   a.theta_x = tx;
   a.theta_y = ty;
@@ -524,6 +535,7 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
   if (!out) return fail(c, LBM_EINVAL, "output must be a device pointer");
+  if (lbm_status st0 = require_attached(c)) return st0;
   hipError_t e = vlbm::launch_moments(c->insts[inst], c->plane, c->cur(), out, c->p.precision,
                                       c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "moments launch");
@@ -585,6 +597,7 @@ lbm_status lbm_totals(lbm_ctx* c, int32_t inst, double* out) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
   if (!out) return fail(c, LBM_EINVAL, "output must be a host pointer to 4 doubles");
+  if (lbm_status st0 = require_attached(c)) return st0;
   const Inst& in = c->insts[inst];
   const long long n = (long long)in.nx * in.ny;
   long long b = (n + 255) / 256;
@@ -622,6 +635,7 @@ size_t lbm_state_bytes(const lbm_ctx* c) {
 lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!dst) return fail(c, LBM_EINVAL, "destination must be a device pointer");
+  if (lbm_status st = require_attached(c)) return st;
   hipError_t e = hipMemcpyAsync(dst, c->cur(), lbm_state_bytes(c), hipMemcpyDeviceToDevice,
                                 c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "get_state copy");
@@ -641,6 +655,27 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src) {
     e = vlbm::launch_lambda_state(c->sc, c->insts.data(), c->n_inst, c->plane, c->cur(),
                                   c->slots, slot, c->p.precision, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "set_state wavespeed");
+  c->detached = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst, double* tx, double* ty) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->n_inst != 1) return fail(c, LBM_ENOTSUP, "lbm_step_between is single-instance only");
+  if (!src || !dst) return fail(c, LBM_EINVAL, "state buffers must be device pointers");
+  if ((!tx) != (!ty)) return fail(c, LBM_EINVAL, "give both theta buffers or neither");
+  const char* s0 = (const char*)src;
+  const char* d0 = (const char*)dst;
+  const size_t nb = lbm_state_bytes(c);
+  if (s0 < d0 + nb && d0 < s0 + nb) return fail(c, LBM_EINVAL, "src and dst must not overlap");
+  if (dst == c->cur()) return fail(c, LBM_EINVAL, "dst must not be the context's current state buffer");
+  vlbm::StepArgs a = make_args(c, src, dst, (int)(c->step % 3));
+  a.theta_x = tx;
+  a.theta_y = ty;
+  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  c->step += 1;
+  c->detached = true;
   return LBM_OK;
 }
 
@@ -696,6 +731,7 @@ lbm_status lbm_get_grid(const lbm_ctx* c, int32_t* groups_per_cu, int32_t* group
 
 lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (lbm_status st0 = require_attached(c)) return st0;
   char key[160];
   long long cells = c->plane;
   snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d", c->n_inst, c->insts[0].nx,

@@ -313,7 +313,7 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
 // face evaluation per row).  The strip to the west evaluates that same face
 // with the same inputs and code, so both cells of a strip-edge face see the
 // same theta.
-template <class T, class C, int LIMS>
+template <class T, class C, int LIMS, bool TH>
 __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                             int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -456,7 +456,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       n_guard += gw;
       n_lim += (th_edge < 1.0);
     }
-    if (LIMS == 0 && A.theta_x) {
+    if (TH || (LIMS == 0 && A.theta_x)) {
       if (row0 && first) A.theta_x[(long long)L * (nx + 1) + x0] = th_edge;
       if (row0 && gi + 1 <= nx) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row0 || row1) && L >= 0 && L <= ny) A.theta_y[(long long)L * nx + gi] = thy;
@@ -545,7 +545,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
 // rho, m_1 of x0 + 65.  From them each evaluates the bounds of its halo cell,
 // and lane 0 the west edge face x0 - 1/2, with the same expressions as every
 // other lane, so both strips beside an edge face see the same theta.
-template <class T, class C, int LIMS>
+template <class T, class C, int LIMS, bool TH>
 __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                           int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -763,7 +763,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       n_guard += gw;
       n_lim += (th_edge < 1.0);
     }
-    if (LIMS == 0 && A.theta_x) {
+    if (TH || (LIMS == 0 && A.theta_x)) {
       if (row1 && first) A.theta_x[(long long)(L - 1) * (nx + 1) + x0] = th_edge;
       if (row1 && gi + 1 <= nx) A.theta_x[(long long)(L - 1) * (nx + 1) + gi + 1] = thx;
       if (lane_out && (row1 || row2) && L - 1 >= 0 && L - 1 <= ny)
@@ -874,7 +874,12 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp);
 }
 
-template <class T, class C, bool LMP, int WPE, int LIMS>
+// The step kernel: T the state's storage type, C its arithmetic type, LMP the
+// bounds-limited march, WPE the waves per SIMD the registers are sized for,
+// LIMS a limiter set fixed at compile time (0: read from the scheme) and TH
+// whether the face factors are written (with LIMS = 0 they are written
+// whenever A.theta_x is set).
+template <class T, class C, bool LMP, int WPE, int LIMS, bool TH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
@@ -902,9 +907,9 @@ void step_kernel(StepArgs A) {
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
     if (LMP)
-      march_lmp<T, C, LIMS>(A, in, A.slots + ii, xs, ys, lane);
+      march_lmp<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane);
     else
-      march_short<T, C, LIMS>(A, in, A.slots + ii, xs, ys, lane);
+      march_short<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane);
   }
 }
 
@@ -1076,22 +1081,25 @@ int grid_for_reduce(long long n) { return grid_for(n, 1024); }
 }  // namespace
 
 // Step launch.  The benchmarked limiter sets (PP + pressure; PP + LMP +
-// pressure) of the second-order scheme without sponge layers or face output
-// run kernels with the set fixed at compile time (same results; A/B on one
-// box: 2% faster in float64 and on the ensembles, 4% on the LMP runs); all
-// other configurations run the general kernels.
+// pressure) of the second-order scheme without sponge layers run kernels
+// with the set, and whether the face factors are written, fixed at compile
+// time (same results; A/B on one box: 2% faster in float64 and on the
+// ensembles, 4% on the LMP runs); all other configurations run the general
+// kernels.
 template <class T, bool LMP, int WPE>
 static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
-  if (lims == kFixed)
-    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed>), grid, block, 0, s, a);
+  if (lims == kFixed && a.theta_x)
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, true>), grid, block, 0, s, a);
+  else if (lims == kFixed)
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, false>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false>), grid, block, 0, s, a);
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
-  const int lims = (a.sc.order == 2 && a.sc.sponge == 0 && a.sc.eps <= 1e-12 && !a.theta_x) ? a.sc.limiters : 0;
+  const int lims = (a.sc.order == 2 && a.sc.sponge == 0 && a.sc.eps <= 1e-12) ? a.sc.limiters : 0;
   const dim3 block(64 * a.waves_per_group);
   const dim3 grid(a.groups);
   if (precision == 0) {

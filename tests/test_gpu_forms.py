@@ -142,6 +142,51 @@ def _dot(a, b):
     return float(np.sum(a * b))
 
 
+@pytest.mark.parametrize("prec,lims", [(B.LBM_FP64, 1 | 8), (B.LBM_FP64, 1 | 2 | 8), (B.LBM_FP32_STATE, 1 | 8)])
+def test_step_between_equals_steps(gpu, prec, lims):
+    """Steps between caller buffers (lbm_step_between) give the states, face
+    factors and scalars of the context's own steps bit for bit; meanwhile the
+    calls that read the context's own state are refused, and lbm_set_state
+    takes the context back to its buffers."""
+    u0 = np.ascontiguousarray(cases.riemann4(130, seed=4)[:, :70, :])
+    kw = dict(precision=prec, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1)
+    a = solver(u0, **kw)
+    b = solver(u0, **kw)
+    ny, nx = 70, 130
+    f64 = gpu.float64
+    buf = [b.get_state()]
+    for i in range(6):
+        tx, ty = a.step_theta()
+        if i % 2 == 0:
+            bx = gpu.empty((ny, nx + 1), dtype=f64, device="cuda")
+            by = gpu.empty((ny + 1, nx), dtype=f64, device="cuda")
+            dst = gpu.empty_like(buf[0])
+            B.lbm_step_between(b.ctx, buf[-1], dst, bx, by)
+            assert gpu.equal(tx, bx) and gpu.equal(ty, by)
+        else:
+            dst = gpu.empty_like(buf[0])
+            B.lbm_step_between(b.ctx, buf[-1], dst)
+        buf.append(dst)
+        assert gpu.equal(a.get_state(), dst), i
+    da, db = a.diagnostics(), b.diagnostics()
+    for k in ("lam", "t", "step", "n_limited", "n_guard", "n_bad"):
+        assert da[k] == db[k], k
+    for call in (lambda: b.get_state(), lambda: b.step(1), lambda: b.moments(),
+                 lambda: b.totals(), lambda: b.step_theta()):
+        with pytest.raises(B.LbmError) as e:
+            call()
+        assert e.value.status == B.LBM_EINVAL
+    with pytest.raises(B.LbmError) as e:  # overlapping buffers
+        B.lbm_step_between(b.ctx, buf[-1], buf[-1])
+    assert e.value.status == B.LBM_EINVAL
+    b.set_state(buf[-1])
+    a.step(3)
+    b.step(3)
+    assert gpu.equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("lims", [1 | 8, 1 | 2 | 8])
 def test_step_adjoint_dot_product(gpu, lims):
     """<J v, w> from the oracle's complex-step tangent of the step with theta

@@ -161,22 +161,29 @@ def test_fp32_state_step_shapes(case, gpu):
 
 @pytest.mark.parametrize("prec,lims", [(B.LBM_FP64, 1 | 8), (B.LBM_FP64, 1 | 2 | 8),
                                        (B.LBM_FP32_STATE, 1 | 8), (B.LBM_FP32_STATE, 1 | 2 | 8)])
-def test_fixed_limiter_kernels_equal_general(prec, lims):
-    """The kernels with the limiter set fixed at compile time (plain steps
-    with PP + pressure or PP + LMP + pressure) and the general kernels (the
-    same steps with face output) give the same states and counters bit for
-    bit, on a 200 x 131 outflow grid with ragged strips."""
+def test_fixed_limiter_kernels(prec, lims):
+    """The kernels with the limiter set fixed at compile time (PP + pressure,
+    PP + LMP + pressure), with and without face output (plain steps and
+    lbm_step_theta), give the same states and counters bit for bit, and in
+    float64 the oracle's states, on a 200 x 131 outflow grid with ragged
+    strips (the general kernels meet the oracle in the face-factor cases with
+    the other limiter sets)."""
     u0 = np.ascontiguousarray(cases.riemann4(200, seed=21)[:, :131, :])
-    kw = dict(precision=prec, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1)
-    a = Solver(u0, **kw)
-    b = Solver(u0, **kw)
+    ocfg = oracle.Config(nx=200, ny=131, dx=1.0 / 200, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1)
+    a = Solver(u0, precision=prec, **okw(ocfg))
+    b = Solver(u0, precision=prec, **okw(ocfg))
     for _ in range(15):
         a.step(1)
         b.step_theta()
     da, db = a.diagnostics(), b.diagnostics()
-    assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+    G = a.get_state().cpu().numpy()
+    assert np.array_equal(G, b.get_state().cpu().numpy())
     for k in ("n_limited", "n_guard", "n_bad", "n_lmp", "lam", "t"):
         assert da[k] == db[k], k
+    if prec == B.LBM_FP64:
+        S, _ = oracle.init(ocfg, u0)
+        S, _, info, _ = oracle.run(ocfg, S, 15)
+        assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
     a.close()
     b.close()
 
