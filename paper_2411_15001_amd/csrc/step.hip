@@ -201,8 +201,8 @@ __device__ __forceinline__ void put(T* p, T v) {
 // Store of value v at byte offset voff of the row that starts at the
 // wave-uniform address `row` and holds `bytes` bytes, through a buffer
 // resource: the hardware drops the lanes whose offset lies beyond the row
-// (columns past the instance's edge) and every lane when bytes = 0 (a row the
-// strip does not produce).  The store is thus issued on every path, and the
+// (columns past the instance's edge, which pass 0xFFFFFFFF) and every lane
+// when bytes = 0 (a row the strip does not produce).  The store is thus issued on every path, and the
 // wait for the next prefetched row, which the compiler otherwise extends over
 // stores issued under a condition, leaves these in flight.  Non-temporal, as
 // put() with the float32 state.  Used by the short march with the float32
@@ -487,7 +487,9 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
         // the row from the plane base and its size in bytes (0: no store)
         const long long r0 = row0 ? (long long)L * nx : 0, r1 = row1 ? (long long)(L - 1) * nx : 0;
         const unsigned rb0 = row0 ? unx * 4u : 0u, rb1 = row1 ? unx * 4u : 0u;
-        const unsigned voff = (unsigned)gi * 4u;
+        // columns past the edge get an offset beyond any row (4 gi itself
+        // could wrap around 2^32 when nx is close to 2^30)
+        const unsigned voff = lane_out ? (unsigned)gi * 4u : 0xFFFFFFFFu;
         put_row(dbase + (4 + c) * P + r0, rb0, voff, (T)u1n);
         put_row(dbase + (8 + c) * P + r0, rb0, voff, (T)u2n);
         put_row(dbase + (12 + c) * P + r0, rb0, voff, (T)u3n);
