@@ -1,0 +1,116 @@
+"""Validation problems of Section 4 on the GPU: the LeBlanc shock tube, the
+Shu-Osher problem and the near-vacuum isentropic wave run to the paper's
+final times with the PP, LMP and RLMP density bounds (each with pressure
+positivity), and the Lax-Liu configuration 3 at 400^2.  Each run must stay
+admissible at every step and end bit for bit on the oracle's state (the
+oracle steps until it passes the final time; the GPU takes the same number of
+steps)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_15001_amd import binding as B
+from paper_2411_15001_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.lib()
+    return torch
+
+
+def Solver(*a, **k):
+    from paper_2411_15001_amd.solver import Solver as S
+
+    return S(*a, **k)
+
+
+def okw(ocfg):
+    return dict(dx=ocfg.params().dx, gamma=ocfg.gamma, alpha=ocfg.alpha, order=ocfg.order,
+                limiters=ocfg.limiters, a_mode=ocfg.a_mode, a_beta=ocfg.a_beta,
+                a_fixed=ocfg.a_fixed, bc_x=ocfg.bc_x, bc_y=ocfg.bc_y, sponge=ocfg.sponge,
+                eps=ocfg.eps, rlmp_lo=ocfg.rlmp_lo, rlmp_hi=ocfg.rlmp_hi)
+
+
+def oracle_to(cfg, u0, t_end=None, steps=None):
+    """Oracle state after `steps` steps, or after the first step that
+    reaches t_end; returns (S, steps, t)."""
+    S, _ = oracle.init(cfg, u0)
+    if steps is not None:
+        S, t, _, tot = oracle.run(cfg, S, steps)
+        assert tot[2] == 0
+        return S, steps, t
+    t, n = 0.0, 0
+    while t < t_end:
+        S, t, _, tot = oracle.run(cfg, S, 1, t)
+        assert tot[2] == 0
+        n += 1
+    return S, n, t
+
+
+def check_gpu(u0, cfg, S_ref, n, t_ref):
+    s = Solver(u0, **okw(cfg))
+    s.step(n)
+    d = s.diagnostics()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0  # read before moments() clears them
+    assert abs(d["t"] - t_ref) <= 1e-12 * t_ref
+    G = s.get_state().cpu().numpy()
+    m = s.moments().cpu().numpy()
+    s.close()
+    rho = m[0]
+    p = (cfg.gamma - 1.0) * (m[3] - 0.5 * (m[1] ** 2 + m[2] ** 2) / rho)
+    assert rho.min() > 0.0 and p.min() > 0.0
+    assert np.array_equal(G, S_ref), "max abs diff %.3e" % np.abs(G - S_ref).max()
+
+
+LIMS = {"PP": 1 | 8, "LMP": 2 | 8, "RLMP": 4 | 8}
+
+
+@pytest.mark.parametrize("lim", list(LIMS))
+def test_leblanc(lim):
+    """Section 4.5: gamma = 5/3, density ratio 1e3, pressure ratio 1e6,
+    N = 1000 on [0, 9], outflow, t = 6 (about 3000 steps)."""
+    print("leblanc", lim, flush=True)
+    cfg = oracle.Config(nx=1000, ny=4, dx=9.0 / 1000, gamma=5.0 / 3.0, limiters=LIMS[lim],
+                        bc_x=1, bc_y=0)
+    u0 = cases.leblanc(1000, nrows=4)
+    S, n, t = oracle_to(cfg, u0, t_end=6.0)
+    check_gpu(u0, cfg, S, n, t)
+
+
+@pytest.mark.parametrize("lim", list(LIMS))
+def test_shu_osher(lim):
+    """Section 4.3: N = 800 on [-5, 5], outflow, t = 1.8."""
+    print("shu-osher", lim, flush=True)
+    cfg = oracle.Config(nx=800, ny=4, dx=10.0 / 800, limiters=LIMS[lim], bc_x=1, bc_y=0)
+    u0 = cases.shu_osher(800, nrows=4)
+    S, n, t = oracle_to(cfg, u0, t_end=1.8)
+    check_gpu(u0, cfg, S, n, t)
+
+
+@pytest.mark.parametrize("lim", list(LIMS))
+def test_isentropic_vacuum_wave(lim):
+    """Section 4.4: gamma = 3, minimum density 5e-7, N = 50 on the periodic
+    [-1, 1], t = 0.1."""
+    print("isentropic", lim, flush=True)
+    cfg = oracle.Config(nx=50, ny=4, dx=2.0 / 50, gamma=3.0, limiters=LIMS[lim])
+    u0 = cases.isentropic_vacuum(50, nrows=4)
+    S, n, t = oracle_to(cfg, u0, t_end=0.1)
+    check_gpu(u0, cfg, S, n, t)
+
+
+@pytest.mark.parametrize("lim", ["PP", "LMP"])
+def test_lax_liu_configuration_3(lim):
+    """Section 4.7: configuration 3 of the 2D Riemann problem at 400^2,
+    outflow, 250 steps."""
+    print("lax-liu 3", lim, flush=True)
+    cfg = oracle.Config(nx=400, ny=400, limiters=LIMS[lim] | (1 if lim == "LMP" else 0),
+                        bc_x=1, bc_y=1)
+    u0 = cases.lax_liu3(400)
+    S, n, t = oracle_to(cfg, u0, steps=250)
+    check_gpu(u0, cfg, S, n, t)
