@@ -276,6 +276,29 @@ def test_isentropic_vacuum_wave_exact_solution(orc):
         assert errs[(2, n)] < 0.25 * errs[(1, n)], (n, errs)
 
 
+def test_leblanc_bounds_cure_pp_oscillations(orc):
+    """Section 4.5 (LeBlanc, gamma = 5/3, N = 1000, t = 6): every limiter
+    keeps the solution admissible; the PP blending oscillates between the
+    shock and the contact, which the LMP and RLMP bounds cure: their density
+    L1 distance to the exact Riemann solution is a fraction of PP's."""
+    import riemann_exact
+
+    g, n = 5.0 / 3.0, 1000
+    left, right = (1.0, 0.0, 0.1 * (g - 1.0)), (1e-3, 0.0, 1e-7 * (g - 1.0))
+    x = cases.cell_centres(n, 0.0, 9.0)
+    err = {}
+    for name, lims in (("PP", 1 | 8), ("LMP", 2 | 8), ("RLMP", 4 | 8)):
+        cfg = orc.Config(nx=n, ny=4, dx=9.0 / n, gamma=g, limiters=lims, bc_x=1, bc_y=0)
+        S, _ = orc.init(cfg, cases.leblanc(n, nrows=4))
+        t = 0.0
+        while t < 6.0:
+            S, t, info, tot = orc.run(cfg, S, 1, t)
+            assert tot[2] == 0
+        rho_ex, _, _ = riemann_exact.sample(left, right, g, (x - 3.0) / t)
+        err[name] = np.abs(S[0][0] - rho_ex).sum() / np.abs(rho_ex).sum()
+    assert err["LMP"] < 0.2 * err["PP"] and err["RLMP"] < 0.2 * err["PP"], err
+
+
 # ------------------------------------------------------ P8: LMP bounds
 def test_lmp_bounds_hold(orc):
     n = 40
