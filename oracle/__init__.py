@@ -27,6 +27,8 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = [os.path.join(HERE, "vlbm_oracle.c")]
 DEPS = SOURCES + [os.path.join(HERE, "model.inc"), os.path.join(HERE, "vlbm_oracle.h")]
 
+BND_ZERO_GRADIENT, BND_WALL, BND_DIRICHLET = 0, 1, 2
+WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 RHO_PP = 1
 RHO_LMP = 2
 RHO_RLMP = 4
@@ -65,6 +67,8 @@ class Params(ctypes.Structure):
         ("sponge", ctypes.c_int32),
         ("eps", ctypes.c_double), ("rlmp_lo", ctypes.c_double),
         ("rlmp_hi", ctypes.c_double),
+        ("bnd_kind", ctypes.POINTER(ctypes.c_uint8) * 4),
+        ("bnd_state", ctypes.POINTER(ctypes.c_double) * 4),
     ]
 
 
@@ -139,13 +143,30 @@ class Config:
     eps: float = 1e-16
     rlmp_lo: float = 0.999
     rlmp_hi: float = 1.001
+    # per-side (west, east, south, north) boundary kinds, uint8 [len] or None,
+    # and Dirichlet moments, float64 [4, len] or None
+    bnd_kind: tuple = (None, None, None, None)
+    bnd_state: tuple = (None, None, None, None)
 
     def params(self) -> Params:
         dx = self.dx if self.dx is not None else 1.0 / self.nx
-        return Params(self.nx, self.ny, dx, self.gamma, self.alpha, self.order,
-                      self.limiters, self.a_mode, self.a_beta, self.a_fixed,
-                      self.bc_x, self.bc_y, self.sponge, self.eps, self.rlmp_lo,
-                      self.rlmp_hi)
+        P = Params(self.nx, self.ny, dx, self.gamma, self.alpha, self.order,
+                   self.limiters, self.a_mode, self.a_beta, self.a_fixed,
+                   self.bc_x, self.bc_y, self.sponge, self.eps, self.rlmp_lo,
+                   self.rlmp_hi)
+        keep = []
+        for side in range(4):
+            k, st = self.bnd_kind[side], self.bnd_state[side]
+            if k is not None:
+                k = np.ascontiguousarray(k, dtype=np.uint8)
+                keep.append(k)
+                P.bnd_kind[side] = k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            if st is not None:
+                st = np.ascontiguousarray(st, dtype=np.float64)
+                keep.append(st)
+                P.bnd_state[side] = st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        P._keep = keep  # the arrays outlive the call that receives P
+        return P
 
 
 def flux(u, gamma=1.4):

@@ -180,7 +180,40 @@ static int check_params(const orc_params* P) {
   if (P->bc_x < 0 || P->bc_x > 1 || P->bc_y < 0 || P->bc_y > 1) return -1;
   if (P->a_mode == ORC_A_FIXED && !(P->a_fixed > 0.0)) return -1;
   if (P->a_mode == ORC_A_DYNAMIC && !(P->a_beta > 0.0)) return -1;
+  for (int side = 0; side < 4; ++side) {
+    const uint8_t* k = P->bnd_kind[side];
+    if (!k) continue;
+    const int ax = side / 2, len = ax == 0 ? P->ny : P->nx, n = ax == 0 ? P->nx : P->ny;
+    if ((ax == 0 ? P->bc_x : P->bc_y) != ORC_BC_OUTFLOW) return -1;
+    for (int r = 0; r < len; ++r) {
+      if (k[r] > ORC_BND_DIRICHLET) return -1;
+      if (k[r] == ORC_BND_WALL && n < 2) return -1;
+      if (k[r] == ORC_BND_DIRICHLET && !P->bnd_state[side]) return -1;
+    }
+  }
   return 0;
+}
+
+/* Largest wavespeed of the Dirichlet boundary states (0 if none); counts the
+ * non-admissible ones. */
+static double bnd_lambda(const orc_params* P, int64_t* nbad) {
+  double lam = 0.0;
+  for (int side = 0; side < 4; ++side) {
+    const uint8_t* k = P->bnd_kind[side];
+    if (!k) continue;
+    const int len = side < 2 ? P->ny : P->nx;
+    for (int r = 0; r < len; ++r) {
+      if (k[r] != ORC_BND_DIRICHLET) continue;
+      const double* st = P->bnd_state[side];
+      const double u[4] = {st[r], st[len + r], st[2 * (size_t)len + r], st[3 * (size_t)len + r]};
+      const double l = cell_wavespeed(u, P->gamma);
+      if (l < 0.0)
+        *nbad += 1;
+      else if (l > lam)
+        lam = l;
+    }
+  }
+  return lam;
 }
 
 int orc_init(const orc_params* P, const double* u0, double* S, orc_info* info) {
@@ -255,7 +288,7 @@ int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x
 
   /* S1: lambda^n, a^n, dt^n = dx / a^n (exact streaming), kappa^n. */
   int64_t bad0 = 0;
-  const double lam = orc_lambda(P, S, &bad0);
+  const double lam = dmax(orc_lambda(P, S, &bad0), bnd_lambda(P, &bad0));
   const double a = orc_kinetic_speed(P, lam);
   const double kappa = 0.5 * a * (1.0 - P->alpha);
   const double w = 0.25 * (1.0 - P->alpha);

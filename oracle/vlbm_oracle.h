@@ -22,6 +22,19 @@
  * indirectly), the sponge layer (sponge > 0), the event counters of orc_info
  * (n_guard, n_limited, n_bad), and evaluating M_k with the current a^n without
  * rescaling the distributions when a changes between steps.
+ *
+ * Boundary cells of kind wall or Dirichlet (Section 4.8 states that it sets
+ * boundary states "by setting the distribution to the corresponding
+ * Maxwellian" and uses a reflective symmetry wall, without further detail):
+ * ghost layer g beyond a wall holds the mirror image of interior cell g - 1
+ * (normal momentum negated in the moment slot and in every distribution, the
+ * two distributions moving along the wall normal exchanged); a Dirichlet
+ * ghost holds the given moments u_D with u_k = M_k(u_D; a^n) in both layers.
+ * A ghost cell beyond a corner takes the x-side rule first (at the nearest
+ * row), then the y-side rule.  lambda^n of a step also covers the Dirichlet
+ * states (a^n must satisfy Bouchut's condition for every state the stencil
+ * reads); the initial a^0 of orc_init covers u0 only.  Parity unpinned
+ * except by the symmetry and uniform-flow checks of the tests.
  */
 #ifndef VLBM_ORACLE_H
 #define VLBM_ORACLE_H
@@ -39,6 +52,19 @@
 #define ORC_BC_PERIODIC 0
 #define ORC_BC_OUTFLOW 1
 
+/* Kinds of the boundary cells of a non-periodic side (Section 4.8 uses all
+ * three: Dirichlet states set as Maxwellians, a reflective symmetry wall,
+ * zero-gradient outflow). */
+#define ORC_BND_ZERO_GRADIENT 0
+#define ORC_BND_WALL 1
+#define ORC_BND_DIRICHLET 2
+
+/* Sides of the grid, the index of bnd_kind / bnd_state. */
+#define ORC_WEST 0
+#define ORC_EAST 1
+#define ORC_SOUTH 2
+#define ORC_NORTH 3
+
 typedef struct {
   int32_t nx, ny;
   double dx;
@@ -50,6 +76,14 @@ typedef struct {
   int32_t bc_x, bc_y;
   int32_t sponge;    /* theta = 0 on faces touching this many cells at an outflow wall */
   double eps, rlmp_lo, rlmp_hi;
+  /* Optional per-cell boundary kinds of the four sides (host arrays of ny
+   * entries for west and east, nx for south and north; NULL = every cell
+   * zero-gradient) and the Dirichlet moments (rho, m1, m2, E) of the same
+   * cells, [4][len] (read only where the kind is ORC_BND_DIRICHLET).  Only
+   * on the sides of an axis whose bc is ORC_BC_OUTFLOW; walls need at least
+   * two cells along their axis. */
+  const uint8_t* bnd_kind[4];
+  const double* bnd_state[4];
 } orc_params;
 
 typedef struct {

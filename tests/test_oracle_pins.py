@@ -299,6 +299,102 @@ def test_leblanc_bounds_cure_pp_oscillations(orc):
     assert err["LMP"] < 0.2 * err["PP"] and err["RLMP"] < 0.2 * err["PP"], err
 
 
+# -------------------------------------------- walls and Dirichlet boundaries
+def _mirror_x(u):
+    """Mirror image of moments [4, ny, nx] across a vertical line."""
+    m = u[:, :, ::-1].copy()
+    m[1] = -m[1]
+    return m
+
+
+@pytest.mark.parametrize("lims", [1 | 8, 4 | 8, 1 | 4 | 8])
+def test_walls_equal_mirror_symmetric_periodic_run(orc, lims):
+    """Reflective walls on the west and east sides of a 24-column grid give
+    the left half of the periodic 48-column run whose data are mirror
+    symmetric about its middle (and, by periodicity, about its edge), to
+    round-off; the same across the south and north sides (transposed).  Not
+    for the plain LMP bounds: at the symmetry axis Delta F^rho is exactly 0
+    next to a wall (theta^rho_LMP = 1) but a rounding-level number in the
+    periodic run, where theta^rho_LMP jumps (its dividend vanishes with D at a
+    local extremum), so the two runs part at the axis."""
+    half = np.ascontiguousarray(cases.riemann4(24, seed=7)[:, :16, :])
+    full = np.ascontiguousarray(np.concatenate([half, _mirror_x(half)], axis=2))
+    for axis in ("x", "y"):
+        h, f = half, full
+        if axis == "y":  # transpose: x <-> y, m1 <-> m2
+            tr = lambda u: np.ascontiguousarray(u[[0, 2, 1, 3]].transpose(0, 2, 1))
+            h, f = tr(half), tr(full)
+        ny, nx = h.shape[1], h.shape[2]
+        kinds = [None] * 4
+        if axis == "x":
+            kinds[orc.WEST] = np.full(ny, orc.BND_WALL, np.uint8)
+            kinds[orc.EAST] = np.full(ny, orc.BND_WALL, np.uint8)
+            cw = orc.Config(nx=nx, ny=ny, dx=1.0 / 48, limiters=lims, bc_x=1, bnd_kind=tuple(kinds))
+            cp = orc.Config(nx=2 * nx, ny=ny, dx=1.0 / 48, limiters=lims)
+        else:
+            kinds[orc.SOUTH] = np.full(nx, orc.BND_WALL, np.uint8)
+            kinds[orc.NORTH] = np.full(nx, orc.BND_WALL, np.uint8)
+            cw = orc.Config(nx=nx, ny=ny, dx=1.0 / 48, limiters=lims, bc_y=1, bnd_kind=tuple(kinds))
+            cp = orc.Config(nx=nx, ny=2 * ny, dx=1.0 / 48, limiters=lims)
+        Sw = evolved_state(orc, cw, h, 30)
+        Sp = evolved_state(orc, cp, f, 30)
+        Sp = Sp[:, :, :nx] if axis == "x" else Sp[:, :ny, :]
+        err = np.abs(Sw - Sp).max() / np.abs(Sp).max()
+        assert err < 1e-11, (axis, err)
+
+
+def test_walls_conserve_mass_and_energy(orc):
+    """Walls on all four sides: no mass or energy crosses them, so the
+    totals of rho and E keep their initial values to round-off over 200
+    steps (the momenta are not conserved: the walls push back)."""
+    n = 40
+    kinds = tuple(np.full(n, orc.BND_WALL, np.uint8) for _ in range(4))
+    cfg = orc.Config(nx=n, ny=n, limiters=1 | 2 | 8, bc_x=1, bc_y=1, bnd_kind=kinds)
+    S0, _ = orc.init(cfg, cases.riemann4(n, seed=2))
+    S, _, _, tot = orc.run(cfg, S0, 200)
+    assert tot[2] == 0
+    for c in (0, 3):
+        a, b = math.fsum(S0[c].ravel()), math.fsum(S[c].ravel())
+        assert abs(a - b) <= 1e-13 * abs(a), (c, a, b)
+
+
+def test_dirichlet_uniform_flow_is_preserved(orc):
+    """A uniform moving state with Dirichlet boundaries holding that same
+    state on all four sides stays uniform to round-off (every ghost is the
+    state's Maxwellian split, as the interior is; the moment sum itself
+    rounds, also on a periodic grid)."""
+    n = 20
+    u0 = cases.prim_to_cons(np.ones((n, n)), 0.5, -0.3, 1.0, GAMMA)
+    st = np.array([u0[c, 0, 0] for c in range(4)])
+    kinds = tuple(np.full(n, orc.BND_DIRICHLET, np.uint8) for _ in range(4))
+    states = tuple(np.repeat(st[:, None], n, axis=1) for _ in range(4))
+    cfg = orc.Config(nx=n, ny=n, bc_x=1, bc_y=1, bnd_kind=kinds, bnd_state=states)
+    S0, _ = orc.init(cfg, u0)
+    S, _, _, _ = orc.run(cfg, S0, 25)
+    for q in range(20):
+        assert np.abs(S[q] - S0[q]).max() <= 1e-14 * np.abs(S0[q]).max(), q
+
+
+def test_dirichlet_equals_outflow_until_waves_arrive(orc):
+    """Sod data along y with a fixed kinetic speed: Dirichlet boundaries
+    holding the two initial states give the zero-gradient run bit for bit
+    while the waves are still far from the boundaries (both ghosts then hold
+    the same equilibrium state)."""
+    n = 200
+    u0 = cases.sod_y(n, ncols=4)
+    lam0 = orc.lam(orc.Config(nx=4, ny=n), u0)[0]
+    kinds = [None] * 4
+    states = [None] * 4
+    kinds[orc.SOUTH] = np.full(4, orc.BND_DIRICHLET, np.uint8)
+    kinds[orc.NORTH] = np.full(4, orc.BND_DIRICHLET, np.uint8)
+    states[orc.SOUTH] = np.ascontiguousarray(u0[:, 0, :])
+    states[orc.NORTH] = np.ascontiguousarray(u0[:, -1, :])
+    common = dict(nx=4, ny=n, dx=1.0 / n, limiters=2 | 8, a_mode=orc.A_FIXED, a_fixed=4.4 * lam0, bc_y=1)
+    Sd = evolved_state(orc, orc.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **common), u0, 60)
+    So = evolved_state(orc, orc.Config(**common), u0, 60)
+    assert np.array_equal(Sd, So)
+
+
 # ------------------------------------------------------ P8: LMP bounds
 def test_lmp_bounds_hold(orc):
     n = 40
