@@ -45,6 +45,10 @@
 extern "C" {
 #endif
 
+#define LBM_BND_ZERO_GRADIENT 0
+#define LBM_BND_WALL 1
+#define LBM_BND_DIRICHLET 2
+
 typedef enum {
   LBM_OK = 0,
   LBM_EINVAL = 1,      /* invalid argument (parameters, pointers, sizes) */
@@ -263,6 +267,28 @@ lbm_status lbm_get_launch(const lbm_ctx* ctx, int32_t* strip_rows, int32_t* wave
  * values; changing the mode drops captured graphs. */
 lbm_status lbm_set_strip_mode(lbm_ctx* ctx, int32_t mode);
 lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
+
+/* Boundary cells of a non-periodic side (side 0 west, 1 east, 2 south, 3
+ * north; the side's axis must be LBM_BC_OUTFLOW).  kind_dev: uint8 device
+ * array, one entry per boundary cell (ny for west and east, nx for south and
+ * north), LBM_BND_ZERO_GRADIENT (0, the outflow copy), LBM_BND_WALL (1, a
+ * reflective symmetry wall: the ghost layers mirror the interior, with the
+ * normal momentum negated and the two distributions moving along the normal
+ * exchanged) or LBM_BND_DIRICHLET (2: the ghost layers hold the moments given
+ * in state_dev with their Maxwellians at the current a^n, Section 4.8).
+ * state_dev: float64 [4][len] device array of (rho, m1, m2, E) per cell, read
+ * where the kind is Dirichlet (may be NULL without Dirichlet cells).  A ghost
+ * beyond a corner takes the x-side rule first, then the y-side rule.  Each
+ * step first raises lambda^n by the Dirichlet states, so that a^n satisfies
+ * Bouchut's condition for every state the stencil reads.  The caller owns
+ * both arrays and keeps them alive while the context steps; the states (not
+ * the kinds, which are checked here) may change between steps, e.g. a moving
+ * inflow.  kind_dev = NULL restores zero-gradient cells on that side.  Walls
+ * need two cells along their axis.  Single instance; the adjoint entry points
+ * return LBM_ENOTSUP while any side has a description.  Synchronises; drops
+ * captured graphs. */
+lbm_status lbm_set_boundary(lbm_ctx* ctx, int32_t side, const uint8_t* kind_dev,
+                            const double* state_dev);
 
 /* Grid of the step kernel.  groups_per_cu = 0 (the default) launches one wave
  * per strip; k in [1, 32] launches a persistent grid of at most k workgroups

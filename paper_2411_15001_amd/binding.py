@@ -30,6 +30,10 @@ LBM_A_DYNAMIC = 0
 LBM_A_FIXED = 1
 LBM_BC_PERIODIC = 0
 LBM_BC_OUTFLOW = 1
+LBM_BND_ZERO_GRADIENT = 0
+LBM_BND_WALL = 1
+LBM_BND_DIRICHLET = 2
+LBM_WEST, LBM_EAST, LBM_SOUTH, LBM_NORTH = 0, 1, 2, 3
 LBM_FP64 = 0
 LBM_FP32_STATE = 1
 
@@ -39,7 +43,7 @@ EXPORTS = [
     "lbm_totals",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_between", "lbm_step_adjoint",
     "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
-    "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode",
+    "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode", "lbm_set_boundary",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -112,6 +116,7 @@ def lib():
         L.lbm_get_launch.argtypes = [vp, i32p, i32p]
         L.lbm_set_grid.argtypes = [vp, i32]
         L.lbm_set_strip_mode.argtypes = [vp, i32]
+        L.lbm_set_boundary.argtypes = [vp, i32, vp, vp]
         L.lbm_get_strip_mode.argtypes = [vp, i32p]
         L.lbm_get_grid.argtypes = [vp, i32p, i32p]
         L.lbm_status_string.argtypes = [ctypes.c_int]
@@ -376,6 +381,25 @@ def lbm_set_grid(ctx, groups_per_cu=0):
 
 def lbm_set_strip_mode(ctx, mode=0):
     return _check(lib().lbm_set_strip_mode(ctx, int(mode)), ctx)
+
+
+def lbm_set_boundary(ctx, side, kind=None, state=None):
+    """Boundary cells of one side (0 west, 1 east, 2 south, 3 north): kind a
+    uint8 device tensor of the side's length (LBM_BND_*), state float64
+    [4, len] device tensor of Dirichlet moments (or None); kind None restores
+    zero-gradient cells.  The tensors must outlive the context's steps."""
+    import torch
+
+    nx, ny = _inst_shape(ctx)
+    n = ny if int(side) in (0, 1) else nx
+    kp = sp = None
+    if kind is not None:
+        _require_cuda(kind, torch.uint8, n, "kind")
+        kp = _ptr(kind)
+        if state is not None:
+            _require_cuda(state, torch.float64, 4 * n, "state")
+            sp = _ptr(state)
+    return _check(lib().lbm_set_boundary(ctx, int(side), kp, sp), ctx)
 
 
 def lbm_get_strip_mode(ctx):

@@ -149,6 +149,10 @@ struct lbm_ctx {
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
   int n_cu = 256;       // compute units of the context's device
   bool detached = false;  // the current state lives in a caller buffer (lbm_step_between)
+  const uint8_t* bnd_kind[4] = {};  // lbm_set_boundary (device arrays, caller-owned)
+  const double* bnd_state[4] = {};
+  bool side_dirichlet[4] = {};
+  bool has_bnd = false, has_dirichlet = false;
   std::string err;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
 
@@ -291,13 +295,28 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
   a.xcd_remap = c->xcd;
   a.groups = compute_groups(c);
   a.sc = c->sc;
+  for (int k = 0; k < 4; ++k) {
+    a.bnd_kind[k] = c->bnd_kind[k];
+    a.bnd_state[k] = c->bnd_state[k];
+  }
+  a.bnd = c->has_bnd ? 1 : 0;
   return a;
+}
+
+// A step with Dirichlet boundary cells first raises lambda^n by their states
+// (Bouchut's condition covers every state the stencil reads).
+hipError_t launch_step_with_bnd(const lbm_ctx* c, const vlbm::StepArgs& a) {
+  if (c->has_dirichlet) {
+    hipError_t e = vlbm::launch_bnd_lambda(a, c->insts[0], a.slot, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return vlbm::launch_step(a, c->p.precision, c->stream);
 }
 
 lbm_status launch_one(lbm_ctx* c) {
   if (lbm_status st = require_attached(c)) return st;
   vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
-  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  hipError_t e = launch_step_with_bnd(c, a);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   c->step += 1;
   return LBM_OK;
@@ -525,7 +544,7 @@ lbm_status lbm_step_theta(lbm_ctx* c, double* tx, double* ty) {
   vlbm::StepArgs a = make_args(c, c->cur(), c->other(), (int)(c->step % 3));
   a.theta_x = tx;
   a.theta_y = ty;
-  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  hipError_t e = launch_step_with_bnd(c, a);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   c->step += 1;
   return LBM_OK;
@@ -672,7 +691,7 @@ lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst, double* tx, 
   vlbm::StepArgs a = make_args(c, src, dst, (int)(c->step % 3));
   a.theta_x = tx;
   a.theta_y = ty;
-  hipError_t e = vlbm::launch_step(a, c->p.precision, c->stream);
+  hipError_t e = launch_step_with_bnd(c, a);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   c->step += 1;
   c->detached = true;
@@ -697,6 +716,42 @@ lbm_status lbm_set_strip_mode(lbm_ctx* c, int32_t mode) {
   if (mode != 0 && mode != 1) return fail(c, LBM_EINVAL, "strip mode must be 0 or 1");
   c->strip_mode = mode;
   return rebuild_launch(c);
+}
+
+lbm_status lbm_set_boundary(lbm_ctx* c, int32_t side, const uint8_t* kind, const double* state) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (side < 0 || side > 3) return fail(c, LBM_EINVAL, "side must be 0 (west), 1 (east), 2 (south) or 3 (north)");
+  if (c->n_inst != 1) return fail(c, LBM_ENOTSUP, "boundary descriptions are single-instance only");
+  const int ax = side / 2;
+  if ((ax == 0 ? c->p.bc_x : c->p.bc_y) != LBM_BC_OUTFLOW)
+    return fail(c, LBM_EINVAL, "boundary descriptions need the side's axis to be non-periodic (LBM_BC_OUTFLOW)");
+  const Inst& in = c->insts[0];
+  const int len = ax == 0 ? in.ny : in.nx, n = ax == 0 ? in.nx : in.ny;
+  bool dirichlet = false;
+  if (kind) {
+    std::vector<uint8_t> h((size_t)len);
+    hipError_t e = hipMemcpyAsync(h.data(), kind, (size_t)len, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reading boundary kinds");
+    for (int r = 0; r < len; ++r) {
+      if (h[r] > vlbm::BND_DIRICHLET) return fail(c, LBM_EINVAL, "unknown boundary kind");
+      if (h[r] == vlbm::BND_WALL && n < 2) return fail(c, LBM_EINVAL, "a wall needs two cells along its axis");
+      dirichlet |= h[r] == vlbm::BND_DIRICHLET;
+    }
+    if (dirichlet && !state) return fail(c, LBM_EINVAL, "Dirichlet cells need a state array");
+  }
+  c->bnd_kind[side] = kind;
+  c->bnd_state[side] = kind ? state : nullptr;
+  c->side_dirichlet[side] = dirichlet;
+  c->has_bnd = false;
+  c->has_dirichlet = false;
+  for (int k = 0; k < 4; ++k) {
+    c->has_bnd |= c->bnd_kind[k] != nullptr;
+    c->has_dirichlet |= c->side_dirichlet[k];
+  }
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return LBM_OK;
 }
 
 lbm_status lbm_get_strip_mode(const lbm_ctx* c, int32_t* mode) {
@@ -916,6 +971,7 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (c->has_bnd) return fail(c, LBM_ENOTSUP, "the adjoint does not cover wall or Dirichlet boundary cells");
   if (!U || !Ub1 || !Ub0) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())
@@ -990,6 +1046,7 @@ extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const doubl
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (c->has_bnd) return fail(c, LBM_ENOTSUP, "the adjoint does not cover wall or Dirichlet boundary cells");
   if (!u0 || !Ub0 || !u0b) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   Slots* save = (Slots*)(c->ws + c->lay.slots_save);
   hipError_t e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);

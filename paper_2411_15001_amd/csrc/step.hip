@@ -303,6 +303,79 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
   return k;
 }
 
+// Boundary cells with a kind per cell (reflective wall, Dirichlet state,
+// zero-gradient): the state of cell (i, j) of the grid extended by two ghost
+// layers, -2 <= i <= nx + 1 and -2 <= j <= ny + 1.  The x sides act first (at
+// the row facing the ghost, wrapped or nearest), then the y sides.  A wall
+// ghost is the mirror image of the interior cell as far inside as the ghost
+// is outside (the normal momentum changes sign in every slot, and the two
+// distributions moving along the normal trade places); a Dirichlet ghost is
+// the given moments u_D with u_k = M_k(u_D; a^n) (Example 1), the state the
+// boundary is set to in Section 4.8; zero-gradient copies the boundary cell
+// (Section 4.2).  Walls need two cells along their axis.
+template <class T>
+__device__ __forceinline__ void reflect_slots(T s[20], int ax) {
+  const int c = 1 + ax, k0 = 1 + 2 * ax;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s[4 * q + c] = -s[4 * q + c];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T t = s[4 * k0 + k];
+    s[4 * k0 + k] = s[4 * (k0 + 1) + k];
+    s[4 * (k0 + 1) + k] = t;
+  }
+}
+
+template <class T, class C>
+__device__ void bnd_cell(const StepArgs& A, const Inst& in, const T* __restrict__ sbase, long long P,
+                         int i, int j, const StepConst<T, C>& K, T out[20]) {
+  const Scheme& sc = A.sc;
+  const int nx = in.nx, ny = in.ny;
+  bool refl_x = false, refl_y = false;
+  for (int ax = 0; ax < 2; ++ax) {
+    const int n = ax == 0 ? nx : ny;
+    int& idx = ax == 0 ? i : j;
+    if (idx >= 0 && idx < n) continue;
+    if ((ax == 0 ? sc.bc_x : sc.bc_y) == 0) {
+      idx = map_index(idx, n, 0);
+      continue;
+    }
+    const int side = 2 * ax + (idx < 0 ? 0 : 1);
+    const int other = ax == 0 ? map_index(j, ny, sc.bc_y) : i;
+    const int len = ax == 0 ? ny : nx;
+    const int kind = A.bnd_kind[side] ? (int)A.bnd_kind[side][other] : BND_ZERO_GRADIENT;
+    if (kind == BND_DIRICHLET) {
+      const double* st = A.bnd_state[side];
+      C u[4], f[4], g[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) u[c] = (C)st[(long long)c * len + other];
+      fluxes(u, K.gm1, f, g);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        out[c] = (T)u[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[4 + 4 * k + c] = (T)maxw(k, u[c], f[c], g[c], K.w, K.r2a);
+      }
+      if (refl_x) reflect_slots(out, 0);
+      return;
+    }
+    if (kind == BND_WALL) {
+      idx = idx < 0 ? -1 - idx : 2 * n - 1 - idx;
+      if (ax == 0)
+        refl_x = true;
+      else
+        refl_y = true;
+    } else {
+      idx = idx < 0 ? 0 : n - 1;
+    }
+  }
+  const unsigned o = (unsigned)j * (unsigned)nx + (unsigned)i;
+#pragma unroll
+  for (int q = 0; q < 20; ++q) out[q] = (sbase + q * P)[o];
+  if (refl_y) reflect_slots(out, 1);
+  if (refl_x) reflect_slots(out, 0);
+}
+
 // Strip march for limiter sets without density bounds (PP, pressure,
 // unlimited, first order).  Both face factors of row L are known as soon as
 // the row arrives, so iteration L completes row L - 1.  Strips are 64 columns
@@ -313,7 +386,7 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
 // face evaluation per row).  The strip to the west evaluates that same face
 // with the same inputs and code, so both cells of a strip-edge face see the
 // same theta.
-template <class T, class C, int LIMS, bool TH>
+template <class T, class C, int LIMS, bool TH, bool BND>
 __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                             int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -353,7 +426,29 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   unsigned n_bad = 0, n_guard = 0, n_lim = 0;
 
   T raw[20], hraw[8];
-  {
+  // with boundary descriptions, ghost rows, columns past the edge and the
+  // halo columns come from bnd_cell
+  auto bnd_load = [&](const int R) {
+    if (R < 0 || R >= ny || !lane_out) {
+      bnd_cell<T, C>(A, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
+    } else {
+      const unsigned o = (unsigned)R * unx + (unsigned)ci;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+    }
+    if (first || last) {
+      T h[20];
+      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hraw[q] = h[q];
+        hraw[4 + q] = first ? h[4 + q] : h[8 + q];
+      }
+    }
+  };
+  if constexpr (BND) {
+    bnd_load(y0 - 1);
+  } else {
     const unsigned ro = (unsigned)map_index(y0 - 1, ny, sc.bc_y) * unx;
     const unsigned o = ro + (unsigned)ci;
 #pragma unroll
@@ -380,7 +475,9 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
       hu[c] = (C)hraw[c];
       hk[c] = (C)hraw[4 + c];
     }
-    if (L < y1) {  // prefetch row L + 1
+    if (BND && L < y1) {
+      bnd_load(L + 1);
+    } else if (L < y1) {  // prefetch row L + 1
       const unsigned ro = (unsigned)map_index(L + 1, ny, sc.bc_y) * unx;
       const unsigned o = ro + (unsigned)ci;
 #pragma unroll
@@ -547,7 +644,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
 // rho, m_1 of x0 + 65.  From them each evaluates the bounds of its halo cell,
 // and lane 0 the west edge face x0 - 1/2, with the same expressions as every
 // other lane, so both strips beside an edge face see the same theta.
-template <class T, class C, int LIMS, bool TH>
+template <class T, class C, int LIMS, bool TH, bool BND>
 __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                           int ys, int lane) {
   const Scheme& sc = A.sc;
@@ -619,7 +716,32 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   };
 
   T raw[20], hraw[8] = {}, oraw[2] = {};
-  {
+  // with boundary descriptions, ghost rows, columns past the edge and the
+  // halo columns come from bnd_cell
+  auto bnd_load = [&](const int R) {
+    if (R < 0 || R >= ny || !lane_out) {
+      bnd_cell<T, C>(A, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
+    } else {
+      const unsigned o = (unsigned)R * unx + (unsigned)ci;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) raw[q] = (sbase + q * P)[o];
+    }
+    if (first || last) {
+      T h[20];
+      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hraw[q] = h[q];
+        hraw[4 + q] = first ? h[4 + q] : h[8 + q];
+      }
+      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 2 : min(x0 + 65, nx + 1), R, K, h);
+      oraw[0] = h[0];
+      oraw[1] = h[1];
+    }
+  };
+  if constexpr (BND) {
+    bnd_load(y0 - 2);
+  } else {
     const unsigned ro = (unsigned)map_index(y0 - 2, ny, sc.bc_y) * unx;
     const unsigned o = ro + (unsigned)ci;
 #pragma unroll
@@ -650,7 +772,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       hk[c] = (C)hraw[4 + c];
     }
     const C orr = (C)oraw[0], om = (C)oraw[1];
-    if (L <= y1) {  // prefetch row L + 1
+    if (BND && L <= y1) {
+      bnd_load(L + 1);
+    } else if (L <= y1) {  // prefetch row L + 1
       const unsigned ro = (unsigned)map_index(L + 1, ny, sc.bc_y) * unx;
       const unsigned o = ro + (unsigned)ci;
 #pragma unroll
@@ -880,8 +1004,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
 // bounds-limited march, WPE the waves per SIMD the registers are sized for,
 // LIMS a limiter set fixed at compile time (0: read from the scheme) and TH
 // whether the face factors are written (with LIMS = 0 they are written
-// whenever A.theta_x is set).
-template <class T, class C, bool LMP, int WPE, int LIMS, bool TH>
+// whenever A.theta_x is set), BND whether boundary descriptions are read
+// (only with LIMS = 0).
+template <class T, class C, bool LMP, int WPE, int LIMS, bool TH, bool BND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
@@ -909,9 +1034,9 @@ void step_kernel(StepArgs A) {
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
     if (LMP)
-      march_lmp<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane);
+      march_lmp<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
     else
-      march_short<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane);
+      march_short<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
   }
 }
 
@@ -1082,21 +1207,52 @@ int grid_for_reduce(long long n) { return grid_for(n, 1024); }
 
 }  // namespace
 
+namespace {
+// Largest wavespeed of the Dirichlet boundary states of one instance, merged
+// into slot `slot` (one workgroup striding over the four sides).
+__global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int nx, int ny, int slot) {
+  double lmax = 0.0;
+  for (int side = 0; side < 4; ++side) {
+    const uint8_t* k = A.bnd_kind[side];
+    if (!k) continue;
+    const int len = side < 2 ? ny : nx;
+    const double* st = A.bnd_state[side];
+    for (int r = threadIdx.x; r < len; r += blockDim.x) {
+      if (k[r] != BND_DIRICHLET) continue;
+      const double l = cell_wavespeed(st[r], st[(long long)len + r], st[2LL * len + r],
+                                      st[3LL * len + r], A.sc.gamma);
+      lmax = vmax(lmax, l);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+  if ((threadIdx.x & 63) == 0 && lmax > 0.0) raise_lambda(&A.slots[0].lam[slot], lmax);
+}
+}  // namespace
+
 // Step launch.  The benchmarked limiter sets (PP + pressure; PP + LMP +
 // pressure) of the second-order scheme without sponge layers run kernels
 // with the set, and whether the face factors are written, fixed at compile
 // time (same results; A/B on one box: 2% faster in float64 and on the
 // ensembles, 4% on the LMP runs); all other configurations run the general
-// kernels.
+// kernels, and a grid with boundary descriptions the general kernels that
+// read them.
 template <class T, bool LMP, int WPE>
 static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
-  if (lims == kFixed && a.theta_x)
-    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, true>), grid, block, 0, s, a);
+  if (a.bnd)
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false, true>), grid, block, 0, s, a);
+  else if (lims == kFixed && a.theta_x)
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, true, false>), grid, block, 0, s, a);
   else if (lims == kFixed)
-    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, kFixed, false, false>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false, false>), grid, block, 0, s, a);
+}
+
+hipError_t launch_bnd_lambda(const StepArgs& a, const Inst& in, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(bnd_lambda_kernel, dim3(1), dim3(256), 0, s, a, in.nx, in.ny, slot);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {

@@ -49,8 +49,15 @@ struct StepArgs {
   int groups;             // launched workgroups
   double* theta_x;        // optional face output (single instance)
   double* theta_y;
+  // per-cell boundary kinds and Dirichlet moments of the four sides (west,
+  // east, south, north; single instance; null: zero-gradient), see lbm_set_boundary
+  const uint8_t* bnd_kind[4];
+  const double* bnd_state[4];
+  int bnd;                // 1 if any side has a boundary description
   Scheme sc;
 };
+
+enum { BND_ZERO_GRADIENT = 0, BND_WALL = 1, BND_DIRICHLET = 2 };
 
 // Launchers (step.hip).
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s);
@@ -67,6 +74,9 @@ hipError_t launch_moments(const Inst& in, long long plane, const void* S,
 hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
                          int blocks, int precision, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
+// Raises slots->lam[slot] to the largest wavespeed of the Dirichlet boundary
+// states of a single instance (one workgroup).
+hipError_t launch_bnd_lambda(const StepArgs& a, const Inst& in, int slot, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s);
 // Adjoint (adjoint.hip).
 hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane,

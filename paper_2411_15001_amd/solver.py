@@ -92,6 +92,29 @@ class Solver:
         strip), strip mode (1 = heights matched to each instance))"""
         return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0], B.lbm_get_strip_mode(self.ctx))
 
+    def set_boundary(self, side, kind=None, state=None):
+        """Boundary cells of one side (B.LBM_WEST ... B.LBM_NORTH): kind uint8
+        [len] (B.LBM_BND_*), state float64 [4, len] Dirichlet moments; numpy
+        arrays are copied to the device and kept by the solver (update a
+        moving state with set_boundary again, or in place on
+        self.boundary[side][1])."""
+        import torch
+
+        if not hasattr(self, "boundary"):
+            self.boundary = {}
+        if kind is None:
+            B.lbm_set_boundary(self.ctx, side)
+            self.boundary.pop(side, None)
+            return
+        if isinstance(kind, np.ndarray):
+            kind = torch.from_numpy(np.ascontiguousarray(kind, dtype=np.uint8)).cuda()
+        k = kind
+        st = None
+        if state is not None:
+            st = _as_device(state, torch).contiguous()
+        B.lbm_set_boundary(self.ctx, side, k.contiguous(), st)
+        self.boundary[side] = (k, st)
+
     def close(self):
         if getattr(self, "ctx", None) is not None:
             B.lbm_destroy(self.ctx)

@@ -1,0 +1,253 @@
+"""Wall and Dirichlet boundary cells on the GPU against the oracle: face
+factors and new states bit for bit over mixes of kinds per side (corners,
+ragged strips, tiny grids, the bounds-limited march), a description of
+zero-gradient cells equal to none, and the paper's double Mach reflection and
+Mach 80 / Mach 2000 jets (Section 4.8) run step by step with their moving or
+fixed inflow states."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_15001_amd import binding as B
+from paper_2411_15001_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+W, E, S_, N = 0, 1, 2, 3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.lib()
+    return torch
+
+
+def Solver(*a, **k):
+    from paper_2411_15001_amd.solver import Solver as S
+
+    return S(*a, **k)
+
+
+def okw(ocfg):
+    return dict(dx=ocfg.params().dx, gamma=ocfg.gamma, alpha=ocfg.alpha, order=ocfg.order,
+                limiters=ocfg.limiters, a_mode=ocfg.a_mode, a_beta=ocfg.a_beta,
+                a_fixed=ocfg.a_fixed, bc_x=ocfg.bc_x, bc_y=ocfg.bc_y, sponge=ocfg.sponge,
+                eps=ocfg.eps, rlmp_lo=ocfg.rlmp_lo, rlmp_hi=ocfg.rlmp_hi)
+
+
+def prim(rho, v1, v2, p, gamma=1.4):
+    return np.array([rho, rho * v1, rho * v2, p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2)])
+
+
+def sides_for(pattern, nx, ny, rng):
+    """Kinds and Dirichlet states per side from a 4-letter pattern (w: wall,
+    d: Dirichlet with random admissible states, m: mixed kinds along the
+    side, z: zero-gradient description, -: none)."""
+    kinds, states = [None] * 4, [None] * 4
+    for side, c in enumerate(pattern):
+        n = ny if side < 2 else nx
+        if c == "-":
+            continue
+        if c == "w":
+            k = np.full(n, 1, np.uint8)
+        elif c == "d":
+            k = np.full(n, 2, np.uint8)
+        elif c == "z":
+            k = np.zeros(n, np.uint8)
+        else:
+            k = rng.integers(0, 3, size=n).astype(np.uint8)
+        kinds[side] = k
+        if (k == 2).any():
+            rho = rng.uniform(0.3, 1.5, n)
+            st = prim(rho, rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0.2, 1.5, n))
+            states[side] = np.ascontiguousarray(st)
+    return kinds, states
+
+
+def gpu_solver(u0, ocfg, kinds, states, **kw):
+    s = Solver(u0, **okw(ocfg), **kw)
+    for side in range(4):
+        if kinds[side] is not None:
+            s.set_boundary(side, kinds[side], states[side])
+    return s
+
+
+CASES = [
+    # (nx, ny, limiters, pattern W E S N, evolve steps)
+    (100, 70, 1 | 8, "ww--", 6),
+    (100, 70, 1 | 8, "--ww", 6),
+    (130, 45, 1 | 2 | 8, "wwww", 8),
+    (64, 64, 4 | 8, "dwmz", 6),
+    (150, 40, 1 | 2 | 8, "mmmm", 8),
+    (70, 33, 2 | 8, "zdwd", 5),
+    (2, 30, 1 | 2 | 8, "wwdm", 5),
+    (40, 3, 1 | 8, "mdww", 4),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%dx%d-l%d-%s" % c[:4])
+def test_boundary_theta_and_state_bitwise(case, gpu):
+    nx, ny, lims, pattern, ev = case
+    print("boundary case", case, flush=True)
+    rng = np.random.default_rng([nx, ny, lims])
+    u0 = np.ascontiguousarray(cases.riemann4(max(nx, ny), seed=5)[:, :ny, :nx])
+    kinds, states = sides_for(pattern, nx, ny, rng)
+    ocfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / max(nx, ny), limiters=lims, bc_x=1, bc_y=1,
+                         bnd_kind=tuple(kinds), bnd_state=tuple(states))
+    S0, _ = oracle.init(ocfg, u0)
+    S, _, _, tot = oracle.run(ocfg, S0, ev)
+    assert tot[2] == 0
+    S1, tx, ty, info = oracle.step(ocfg, S)
+    # plain steps from u0
+    s = gpu_solver(u0, ocfg, kinds, states)
+    s.step(ev)
+    assert np.array_equal(s.get_state().cpu().numpy(), S)
+    # one step with face output from the oracle's state (the counters of the
+    # steps above are cleared first)
+    s.moments(check=False)
+    s.set_state(gpu.from_numpy(S).cuda())
+    gtx, gty = s.step_theta()
+    assert np.array_equal(gtx.cpu().numpy(), tx)
+    assert np.array_equal(gty.cpu().numpy(), ty)
+    assert np.array_equal(s.get_state().cpu().numpy(), S1)
+    d = s.diagnostics()
+    assert d["n_limited"] == info.n_limited and d["n_guard"] == info.n_guard
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_step_adjoint(s.ctx, gpu.from_numpy(S).cuda(), gpu.zeros(S.shape, dtype=gpu.float64, device="cuda"),
+                           gpu.zeros(S.shape, dtype=gpu.float64, device="cuda"))
+    assert e.value.status == B.LBM_ENOTSUP
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [B.LBM_FP64, B.LBM_FP32_STATE])
+def test_zero_gradient_description_equals_none(prec, gpu):
+    """Describing every boundary cell as zero-gradient reproduces the run
+    without descriptions bit for bit (the kernels that read descriptions
+    against the plain ones)."""
+    nx, ny = 150, 90
+    u0 = np.ascontiguousarray(cases.riemann4(150, seed=9)[:, :ny, :nx])
+    for lims in (1 | 8, 1 | 2 | 8):
+        kw = dict(precision=prec, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1)
+        a = Solver(u0, **kw)
+        b = Solver(u0, **kw)
+        for side in range(4):
+            b.set_boundary(side, np.zeros(ny if side < 2 else nx, np.uint8))
+        a.step(20)
+        b.step(20)
+        assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy()), lims
+        a.close()
+        b.close()
+
+
+def test_boundary_errors(gpu):
+    u0 = cases.riemann4(32, seed=1)
+    s = Solver(u0)  # periodic
+    with pytest.raises(B.LbmError) as e:
+        s.set_boundary(W, np.ones(32, np.uint8))
+    assert e.value.status == B.LBM_EINVAL
+    s.close()
+    s = Solver(u0, bc_x=1, bc_y=1)
+    for kind, state in ((np.full(32, 3, np.uint8), None), (np.full(32, 2, np.uint8), None)):
+        with pytest.raises(B.LbmError) as e:
+            s.set_boundary(S_, kind, state)
+        assert e.value.status == B.LBM_EINVAL
+    with pytest.raises(ValueError):
+        s.set_boundary(N, np.ones(31, np.uint8))
+    s.close()
+
+
+def _dmr_post():
+    return prim(8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
+
+
+def _dmr_pre():
+    return prim(1.4, 0.0, 0.0, 1.0)
+
+
+def _dmr_u0(nx, ny):
+    x = (np.arange(nx) + 0.5) * 3.0 / nx
+    y = (np.arange(ny) + 0.5) * 1.0 / ny
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    post = X < 1.0 / 6.0 + Y / math.sqrt(3.0)
+    u = np.where(post[None], _dmr_post()[:, None, None], _dmr_pre()[:, None, None])
+    return np.ascontiguousarray(u)
+
+
+def _dmr_top(nx, t):
+    x = (np.arange(nx) + 0.5) * 3.0 / nx
+    post = x < 1.0 / 6.0 + (1.0 + 20.0 * t) / math.sqrt(3.0)
+    return np.ascontiguousarray(np.where(post[None], _dmr_post()[:, None], _dmr_pre()[:, None]))
+
+
+def test_double_mach_reflection(gpu):
+    """Section 4.8: Mach 10 shock on [0, 3] x [0, 1] at 240 x 80, LMP and
+    pressure positivity; Dirichlet post-shock states on the west side and on
+    the south side for x < 1/6, a reflective wall on the south side beyond,
+    pre-shock states on the east side and the moving shock's states on the
+    north side (updated every step); 120 steps, admissible, bit-identical to
+    the oracle."""
+    nx, ny, steps = 240, 80, 120
+    u0 = _dmr_u0(nx, ny)
+    x = (np.arange(nx) + 0.5) * 3.0 / nx
+    kinds = [np.full(ny, 2, np.uint8), np.full(ny, 2, np.uint8),
+             np.where(x < 1.0 / 6.0, 2, 1).astype(np.uint8), np.full(nx, 2, np.uint8)]
+    states = [np.repeat(_dmr_post()[:, None], ny, 1), np.repeat(_dmr_pre()[:, None], ny, 1),
+              np.repeat(_dmr_post()[:, None], nx, 1), _dmr_top(nx, 0.0)]
+    states = [np.ascontiguousarray(a) for a in states]
+    base = dict(nx=nx, ny=ny, dx=1.0 / ny, limiters=2 | 8, bc_x=1, bc_y=1)
+    S, _ = oracle.init(oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base), u0)
+    s = gpu_solver(u0, oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base), kinds, states)
+    top = s.boundary[N][1]
+    t = 0.0
+    for _ in range(steps):
+        states[N] = _dmr_top(nx, t)
+        cfg = oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base)
+        S, t_new, info, tot = oracle.run(cfg, S, 1, t)
+        assert tot[2] == 0 and info.bouchut == 0
+        top.copy_(gpu.from_numpy(states[N]))
+        s.step(1)
+        t = t_new
+    d = s.diagnostics()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0
+    assert abs(d["t"] - t) <= 1e-12 * t
+    assert np.array_equal(s.get_state().cpu().numpy(), S)
+    s.close()
+
+
+@pytest.mark.parametrize("mach", [80, 2000])
+def test_astrophysical_jet(mach, gpu):
+    """Section 4.8: jets of Mach 80 ([0, 2] x [-1/2, 1/2]) and 2000
+    ([0, 1] x [-1/4, 1/4]) at 160 x 80, gamma = 5/3, RLMP and pressure
+    positivity; the west side holds the inflow state (5, v, 0, 0.4127) where
+    |y| < 0.05 and the ambient state elsewhere, the other sides are
+    zero-gradient; admissible at every step and bit-identical to the
+    oracle."""
+    g = 5.0 / 3.0
+    nx, ny, steps = 160, 80, 150
+    Lx, Ly = (2.0, 1.0) if mach == 80 else (1.0, 0.5)
+    v = 30.0 if mach == 80 else 800.0
+    amb = prim(0.5, 0.0, 0.0, 0.4127, g)
+    jet = prim(5.0, v, 0.0, 0.4127, g)
+    u0 = np.ascontiguousarray(np.repeat(np.repeat(amb[:, None, None], ny, 1), nx, 2))
+    y = (np.arange(ny) + 0.5) * Ly / ny - 0.5 * Ly
+    west = np.ascontiguousarray(np.where((np.abs(y) < 0.05)[None], jet[:, None], amb[:, None]))
+    kinds = [np.full(ny, 2, np.uint8), None, None, None]
+    states = [west, None, None, None]
+    cfg = oracle.Config(nx=nx, ny=ny, dx=Lx / nx, gamma=g, limiters=4 | 8, bc_x=1, bc_y=1,
+                        bnd_kind=tuple(kinds), bnd_state=tuple(states))
+    S0, _ = oracle.init(cfg, u0)
+    S, t, info, tot = oracle.run(cfg, S0, steps)
+    assert tot[2] == 0 and info.bouchut == 0
+    s = gpu_solver(u0, cfg, kinds, states)
+    s.step(steps)
+    d = s.diagnostics()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0
+    G = s.get_state().cpu().numpy()
+    assert np.array_equal(G, S), "max abs diff %.3e" % np.abs(G - S).max()
+    assert (G[0] > 0).all()
+    s.close()
