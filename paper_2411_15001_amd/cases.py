@@ -216,3 +216,88 @@ def random_admissible(count, seed=0, gamma=GAMMA_AIR, rho_range=(1e-3, 2.0),
     v2 = rng.uniform(*v_range, size=count)
     p = rng.uniform(*p_range, size=count)
     return prim_to_cons(rho, v1, v2, p, gamma)
+
+
+# Side codes of the boundary descriptions (the values of the library's and the
+# oracle's boundary kinds): 1 = reflective wall, 2 = Dirichlet state.
+_WALL, _DIRICHLET = 1, 2
+
+
+def dmr_states(gamma=GAMMA_AIR):
+    """Section 4.8 double Mach reflection: post-shock (8, 8.25 cos 30deg,
+    -8.25 sin 30deg, 116.5) and pre-shock (1.4, 0, 0, 1) states, [4] each."""
+    post = prim_to_cons(8.0, 8.25 * np.cos(np.pi / 6.0), -8.25 * np.sin(np.pi / 6.0), 116.5, gamma)
+    pre = prim_to_cons(1.4, 0.0, 0.0, 1.0, gamma)
+    return post, pre
+
+
+def dmr_shock_x(y, t):
+    """Position on [0, 3] of the incident Mach 10 shock at height y, time t:
+    it meets y = 0 at x = 1/6 at t = 0 at 60 degrees to the x axis and moves
+    at speed 10 along its normal."""
+    return 1.0 / 6.0 + (y + 20.0 * t) / np.sqrt(3.0)
+
+
+def double_mach(nx=1500, ny=500, gamma=GAMMA_AIR):
+    """Section 4.8 double Mach reflection on [0, 3] x [0, 1] (square cells,
+    nx = 3 ny).  Returns (u0, kinds, states): the initial moments and, per
+    side (west, east, south, north), the boundary kinds (uint8) and states
+    [4, n].  Every boundary cell holds the exact solution (the shock moving
+    at its Rankine-Hugoniot speed) at its centre, half a cell outside the
+    domain, except the south cells with x >= 1/6, which are a reflective wall.
+    On the west and on the south that state is the post-shock one at all
+    times; on the east and the north it changes as the shock passes
+    (`double_mach_east`, `double_mach_north` give them at time t; here t = 0)."""
+    post, pre = dmr_states(gamma)
+    x = cell_centres(nx, 0.0, 3.0)
+    y = cell_centres(ny)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    u0 = np.where((X < dmr_shock_x(Y, 0.0))[None], post[:, None, None], pre[:, None, None])
+    kinds = (np.full(ny, _DIRICHLET, np.uint8), np.full(ny, _DIRICHLET, np.uint8),
+             np.where(x < 1.0 / 6.0, _DIRICHLET, _WALL).astype(np.uint8),
+             np.full(nx, _DIRICHLET, np.uint8))
+    states = (np.repeat(post[:, None], ny, 1), double_mach_east(ny, 0.0, gamma),
+              np.repeat(post[:, None], nx, 1), double_mach_north(nx, 0.0, gamma))
+    return (np.ascontiguousarray(u0), kinds, tuple(np.ascontiguousarray(s) for s in states))
+
+
+def double_mach_north(nx, t, gamma=GAMMA_AIR):
+    """North boundary states of the double Mach reflection at time t, at the
+    boundary cells' centres y = 1 + dx/2: post-shock left of the moving
+    shock, pre-shock right of it, [4, nx]."""
+    post, pre = dmr_states(gamma)
+    x = cell_centres(nx, 0.0, 3.0)
+    behind = x < dmr_shock_x(1.0 + 1.5 / nx, t)
+    return np.ascontiguousarray(np.where(behind[None], post[:, None], pre[:, None]))
+
+
+def double_mach_east(ny, t, gamma=GAMMA_AIR):
+    """East boundary states of the double Mach reflection at time t, at the
+    boundary cells' centres x = 3 + dx/2: pre-shock until the shock reaches
+    them (from t of about 0.19 on, top rows first), post-shock after, [4, ny]."""
+    post, pre = dmr_states(gamma)
+    y = cell_centres(ny)
+    behind = 3.0 + 0.5 / ny < dmr_shock_x(y, t)
+    return np.ascontiguousarray(np.where(behind[None], post[:, None], pre[:, None]))
+
+
+def jet(mach, nx=800, ny=400, gamma=5.0 / 3.0):
+    """Section 4.8 astrophysical jets: Mach 80 on [0, 2] x [-1/2, 1/2] with
+    inflow (5, 30, 0, 0.4127), Mach 2000 on [0, 1] x [-1/4, 1/4] with inflow
+    (5, 800, 0, 0.4127), where |y| < 0.05 on the west side; ambient gas
+    (0.5, 0, 0, 0.4127) everywhere else.  Returns (u0, west, dx, t_end): the
+    initial moments, the west side's Dirichlet states [4, ny] (the other
+    sides are zero-gradient), the cell size and the final time of the paper
+    (0.07, resp. 0.001)."""
+    if mach == 80:
+        lx, ly, v, t_end = 2.0, 1.0, 30.0, 0.07
+    elif mach == 2000:
+        lx, ly, v, t_end = 1.0, 0.5, 800.0, 0.001
+    else:
+        raise ValueError("mach must be 80 or 2000")
+    amb = prim_to_cons(0.5, 0.0, 0.0, 0.4127, gamma)
+    inflow = prim_to_cons(5.0, v, 0.0, 0.4127, gamma)
+    u0 = np.repeat(np.repeat(amb[:, None, None], ny, 1), nx, 2)
+    y = cell_centres(ny, -0.5 * ly, 0.5 * ly)
+    west = np.where((np.abs(y) < 0.05)[None], inflow[:, None], amb[:, None])
+    return np.ascontiguousarray(u0), np.ascontiguousarray(west), lx / nx, t_end

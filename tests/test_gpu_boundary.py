@@ -4,7 +4,6 @@ ragged strips, tiny grids, the bounds-limited march), a description of
 zero-gradient cells equal to none, and the paper's double Mach reflection and
 Mach 80 / Mach 2000 jets (Section 4.8) run step by step with their moving or
 fixed inflow states."""
-import math
 
 import numpy as np
 import pytest
@@ -161,55 +160,29 @@ def test_boundary_errors(gpu):
     s.close()
 
 
-def _dmr_post():
-    return prim(8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
-
-
-def _dmr_pre():
-    return prim(1.4, 0.0, 0.0, 1.0)
-
-
-def _dmr_u0(nx, ny):
-    x = (np.arange(nx) + 0.5) * 3.0 / nx
-    y = (np.arange(ny) + 0.5) * 1.0 / ny
-    X, Y = np.meshgrid(x, y, indexing="xy")
-    post = X < 1.0 / 6.0 + Y / math.sqrt(3.0)
-    u = np.where(post[None], _dmr_post()[:, None, None], _dmr_pre()[:, None, None])
-    return np.ascontiguousarray(u)
-
-
-def _dmr_top(nx, t):
-    x = (np.arange(nx) + 0.5) * 3.0 / nx
-    post = x < 1.0 / 6.0 + (1.0 + 20.0 * t) / math.sqrt(3.0)
-    return np.ascontiguousarray(np.where(post[None], _dmr_post()[:, None], _dmr_pre()[:, None]))
-
-
 def test_double_mach_reflection(gpu):
     """Section 4.8: Mach 10 shock on [0, 3] x [0, 1] at 240 x 80, LMP and
-    pressure positivity; Dirichlet post-shock states on the west side and on
-    the south side for x < 1/6, a reflective wall on the south side beyond,
-    pre-shock states on the east side and the moving shock's states on the
-    north side (updated every step); 120 steps, admissible, bit-identical to
-    the oracle."""
+    pressure positivity; Dirichlet states of the exact solution on every
+    side (post-shock on the west and on the south for x < 1/6, the moving
+    shock's states on the east and the north, updated every step), a
+    reflective wall on the south side beyond x = 1/6; 120 steps, admissible,
+    bit-identical to the oracle."""
     nx, ny, steps = 240, 80, 120
-    u0 = _dmr_u0(nx, ny)
-    x = (np.arange(nx) + 0.5) * 3.0 / nx
-    kinds = [np.full(ny, 2, np.uint8), np.full(ny, 2, np.uint8),
-             np.where(x < 1.0 / 6.0, 2, 1).astype(np.uint8), np.full(nx, 2, np.uint8)]
-    states = [np.repeat(_dmr_post()[:, None], ny, 1), np.repeat(_dmr_pre()[:, None], ny, 1),
-              np.repeat(_dmr_post()[:, None], nx, 1), _dmr_top(nx, 0.0)]
-    states = [np.ascontiguousarray(a) for a in states]
+    u0, kinds, states = cases.double_mach(nx, ny)
+    states = list(states)
     base = dict(nx=nx, ny=ny, dx=1.0 / ny, limiters=2 | 8, bc_x=1, bc_y=1)
     S, _ = oracle.init(oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base), u0)
     s = gpu_solver(u0, oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base), kinds, states)
-    top = s.boundary[N][1]
+    top, east = s.boundary[N][1], s.boundary[E][1]
     t = 0.0
     for _ in range(steps):
-        states[N] = _dmr_top(nx, t)
+        states[N] = cases.double_mach_north(nx, t)
+        states[E] = cases.double_mach_east(ny, t)
         cfg = oracle.Config(bnd_kind=tuple(kinds), bnd_state=tuple(states), **base)
         S, t_new, info, tot = oracle.run(cfg, S, 1, t)
         assert tot[2] == 0 and info.bouchut == 0
         top.copy_(gpu.from_numpy(states[N]))
+        east.copy_(gpu.from_numpy(states[E]))
         s.step(1)
         t = t_new
     d = s.diagnostics()
@@ -229,16 +202,10 @@ def test_astrophysical_jet(mach, gpu):
     oracle."""
     g = 5.0 / 3.0
     nx, ny, steps = 160, 80, 150
-    Lx, Ly = (2.0, 1.0) if mach == 80 else (1.0, 0.5)
-    v = 30.0 if mach == 80 else 800.0
-    amb = prim(0.5, 0.0, 0.0, 0.4127, g)
-    jet = prim(5.0, v, 0.0, 0.4127, g)
-    u0 = np.ascontiguousarray(np.repeat(np.repeat(amb[:, None, None], ny, 1), nx, 2))
-    y = (np.arange(ny) + 0.5) * Ly / ny - 0.5 * Ly
-    west = np.ascontiguousarray(np.where((np.abs(y) < 0.05)[None], jet[:, None], amb[:, None]))
+    u0, west, dx, _ = cases.jet(mach, nx, ny)
     kinds = [np.full(ny, 2, np.uint8), None, None, None]
     states = [west, None, None, None]
-    cfg = oracle.Config(nx=nx, ny=ny, dx=Lx / nx, gamma=g, limiters=4 | 8, bc_x=1, bc_y=1,
+    cfg = oracle.Config(nx=nx, ny=ny, dx=dx, gamma=g, limiters=4 | 8, bc_x=1, bc_y=1,
                         bnd_kind=tuple(kinds), bnd_state=tuple(states))
     S0, _ = oracle.init(cfg, u0)
     S, t, info, tot = oracle.run(cfg, S0, steps)
