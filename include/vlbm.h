@@ -281,9 +281,12 @@ lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
  * beyond a corner takes the x-side rule first, then the y-side rule.  Each
  * step first raises lambda^n by the Dirichlet states, so that a^n satisfies
  * Bouchut's condition for every state the stencil reads.  The caller owns
- * both arrays and keeps them alive while the context steps; the states (not
- * the kinds, which are checked here) may change between steps, e.g. a moving
- * inflow.  kind_dev = NULL restores zero-gradient cells on that side.  Walls
+ * both arrays and keeps them alive while the context steps.  The states may
+ * change between steps (e.g. a moving inflow); the kinds are read and checked
+ * by this call and must not change afterwards: call lbm_set_boundary again
+ * after changing them (a kind turned Dirichlet behind the library's back on a
+ * side given no state array would be read from NULL).  kind_dev = NULL
+ * restores zero-gradient cells on that side.  Walls
  * need two cells along their axis.  Single instance; the adjoint entry points
  * return LBM_ENOTSUP while any side has a description.  Synchronises; drops
  * captured graphs. */
