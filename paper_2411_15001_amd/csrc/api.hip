@@ -527,6 +527,9 @@ extern "C" {
 lbm_status lbm_step_graph(lbm_ctx* c, int32_t nsteps) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+  // a graph captured before lbm_step_between would step the context's own,
+  // stale buffers
+  if (lbm_status st = require_attached(c)) return st;
   while (nsteps > 0) {
     const int32_t k = nsteps > kGraphChunk ? kGraphChunk : nsteps;
     const lbm_status st = replay_graph(c, k);
