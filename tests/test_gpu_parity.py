@@ -497,3 +497,35 @@ def test_error_statuses(gpu):
         assert e.value.status == B.LBM_EINVAL
     assert s.launch()[2] == 0
     s.close()
+
+
+@pytest.mark.parametrize("alpha,beta,lims,prec", [(0.75, 1.0, 1 | 8, B.LBM_FP64), (0.6, 2.0, 1 | 2 | 8, B.LBM_FP64),
+                                                  (0.9, 1.5, 4 | 8, B.LBM_FP64), (0.5, 3.0, 2 | 8, B.LBM_FP64),
+                                                  (0.75, 1.25, 1 | 8, B.LBM_FP32_STATE)])
+def test_rest_weight_and_speed_factor_variants(alpha, beta, lims, prec, gpu):
+    """The D2Q5 rest weight alpha in [1/2, 1) (Proposition 3) and the kinetic
+    speed factor beta >= 1 of a = 2 beta lambda / (1 - alpha): face factors
+    and states after 10 steps bit for bit against the oracle (float64), or
+    within 1e-5 relative L1 in density (float32 state); outflow, ragged strips."""
+    nx, ny = 90, 70
+    u0 = np.ascontiguousarray(cases.riemann4(90, seed=11)[:, :ny, :nx])
+    ocfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / 90, alpha=alpha, a_beta=beta, limiters=lims,
+                         bc_x=1, bc_y=1)
+    S0, _ = oracle.init(ocfg, u0)
+    S, _, info, tot = oracle.run(ocfg, S0, 10)
+    assert tot[2] == 0 and info.bouchut == 0
+    s = Solver(u0, precision=prec, **okw(ocfg))
+    s.step(10)
+    d = s.diagnostics()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0
+    if prec == B.LBM_FP64:
+        assert np.array_equal(s.get_state().cpu().numpy(), S)
+        S1, tx, ty, _ = oracle.step(ocfg, S)
+        gtx, gty = s.step_theta()
+        assert np.array_equal(gtx.cpu().numpy(), tx) and np.array_equal(gty.cpu().numpy(), ty)
+        assert np.array_equal(s.get_state().cpu().numpy(), S1)
+    else:
+        rho = s.moments().cpu().numpy()[0]
+        err = np.abs(rho - S[0]).sum() / np.abs(S[0]).sum()  # slot 0: the density
+        assert err < 1e-5, err
+    s.close()
