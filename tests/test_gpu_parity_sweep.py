@@ -144,3 +144,65 @@ def test_sweep_case(i, gpu):
         err = np.abs(rho - S[0]).sum() / np.abs(S[0]).sum()
         assert err < 1e-5, err
     s.close()
+
+
+N_BATCH_CASES = 40
+
+
+def draw_batch_case(i):
+    rng = np.random.default_rng([2411, 15001, 7, i])
+    c = {}
+    n = int(rng.integers(1, 13))
+    c["sizes"] = [(int(rng.choice([1, 5, 33, 64, 65, 128, 130, 200])),
+                   int(rng.choice([1, 4, 17, 64, 100, 131]))) for _ in range(n)]
+    c["lims"] = int(rng.choice(LIMITER_SETS[:6]))
+    c["order"] = 1 if rng.random() < 0.1 else 2
+    c["bc_x"] = int(rng.integers(0, 2))
+    c["bc_y"] = int(rng.integers(0, 2))
+    c["alpha"] = float(rng.choice([0.5, 0.5, 0.7]))
+    c["beta"] = float(rng.choice([1.0, 1.1, 1.5]))
+    c["prec"] = B.LBM_FP32_STATE if rng.random() < 0.3 else B.LBM_FP64
+    c["steps"] = int(rng.integers(2, 8))
+    c["graph_steps"] = int(rng.integers(0, 5))
+    c["launch"] = (int(rng.choice([0, 4, 16, 64])), int(rng.choice([0, 1, 2, 4])))
+    c["grid"] = int(rng.choice([0, 0, 1, 2, 4]))
+    c["mode"] = int(rng.integers(0, 2))
+    c["seed"] = int(rng.integers(0, 1 << 30))
+    return c
+
+
+@pytest.mark.parametrize("i", range(N_BATCH_CASES))
+def test_batch_sweep_case(i, gpu):
+    """An uneven ensemble (one launch per step, then graph replays) against
+    the oracle run of each instance alone (dx = 1/nx per instance): float64
+    moments bit for bit, float32 state to 1e-5 relative L1 in density."""
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    c = draw_batch_case(i)
+    print("batch sweep case", i, c, flush=True)
+    u0s = []
+    for k, (nx, ny) in enumerate(c["sizes"]):
+        u = cases.riemann4(max(nx, ny), rng=np.random.default_rng([c["seed"], k]))
+        u0s.append(np.ascontiguousarray(u[:, :ny, :nx]))
+    kw = dict(limiters=c["lims"], order=c["order"], alpha=c["alpha"], a_beta=c["beta"],
+              bc_x=c["bc_x"], bc_y=c["bc_y"])
+    bs = BatchSolver(u0s, precision=c["prec"], **kw)
+    bs.set_launch(*c["launch"], groups_per_cu=c["grid"], strip_mode=c["mode"])
+    bs.step(c["steps"])
+    bs.step_graph(c["graph_steps"])
+    total = c["steps"] + c["graph_steps"]
+    diags = [bs.diagnostics(k) for k in range(len(u0s))]  # before moments() clears the counters
+    for k, u in enumerate(u0s):
+        ny, nx = u.shape[1:]
+        cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, **kw)
+        S, _ = oracle.init(cfg, u)
+        S, _, _, tot = oracle.run(cfg, S, total)
+        m = bs.moments(k, check=False)[0].cpu().numpy()
+        if c["prec"] == B.LBM_FP64:
+            assert np.array_equal(m, S[0:4], equal_nan=True), (k, nx, ny)
+            d = diags[k]
+            assert d["n_bad"] == tot[2] and d["n_limited"] == tot[1], (k, d, tot)
+        else:
+            err = np.abs(m[0] - S[0]).sum() / np.abs(S[0]).sum()
+            assert err < 1e-5, (k, err)
+    bs.close()
