@@ -206,3 +206,68 @@ def test_batch_sweep_case(i, gpu):
             err = np.abs(m[0] - S[0]).sum() / np.abs(S[0]).sum()
             assert err < 1e-5, (k, err)
     bs.close()
+
+
+N_ADJOINT_CASES = 24
+
+
+def draw_adjoint_case(i):
+    rng = np.random.default_rng([2411, 15001, 13, i])
+    c = {}
+    c["nx"] = int(rng.choice([1, 2, 17, 64, 65, 100]))
+    c["ny"] = int(rng.choice([1, 3, 16, 40, 70]))
+    c["lims"] = int(rng.choice(LIMITER_SETS[:6] + [0]))
+    c["order"] = 1 if rng.random() < 0.2 else 2
+    c["bc_x"] = int(rng.integers(0, 2))
+    c["bc_y"] = int(rng.integers(0, 2))
+    c["sponge"] = int(rng.integers(1, 4)) if (c["bc_x"] or c["bc_y"]) and rng.random() < 0.3 else 0
+    c["alpha"] = float(rng.choice([0.5, 0.6, 0.8]))
+    c["beta"] = float(rng.choice([1.0, 1.1, 2.0]))
+    c["steps"] = int(rng.integers(1, 10))
+    c["seed"] = int(rng.integers(0, 1 << 30))
+    return c
+
+
+@pytest.mark.parametrize("i", range(N_ADJOINT_CASES))
+def test_adjoint_sweep_case(i, gpu):
+    """<J v, w> from the oracle's complex-step tangent of one step (theta and a
+    frozen at the forward values) equals <v, J^T w> from lbm_step_adjoint to
+    1e-12, and lbm_step_adjoint_theta with the face factors of lbm_step_theta
+    equals lbm_step_adjoint bit for bit, over random sizes, limiter sets,
+    orders, axes, sponges, alpha and beta."""
+    torch = gpu
+    c = draw_adjoint_case(i)
+    print("adjoint sweep case", i, c, flush=True)
+    nx, ny = c["nx"], c["ny"]
+    if c["lims"] == 0 and c["order"] == 2:
+        u0 = cases.gaussian_bump(max(nx, ny), seed=c["seed"] % 7, amp=0.2, sigma=0.2)
+    else:
+        u0 = cases.riemann4(max(nx, ny), seed=c["seed"] % 97)
+    u0 = np.ascontiguousarray(u0[:, :ny, :nx])
+    kw = dict(dx=1.0 / max(nx, ny), limiters=c["lims"], order=c["order"], alpha=c["alpha"],
+              a_beta=c["beta"], bc_x=c["bc_x"], bc_y=c["bc_y"], sponge=c["sponge"])
+    cfg = oracle.Config(nx=nx, ny=ny, **kw)
+    S, _ = oracle.init(cfg, u0)
+    S, _, _, tot = oracle.run(cfg, S, c["steps"])
+    _, tx, ty, info = oracle.step(cfg, S)
+    s = Solver(u0, **kw)
+    Ut = torch.from_numpy(S).cuda()
+    rng = np.random.default_rng(c["seed"])
+    v = rng.normal(size=S.shape)
+    w = rng.normal(size=S.shape)
+    h = 1e-30
+    _, im = oracle.step_frozen_cs(cfg, S, h * v, tx, ty, info.a)
+    jv = im / h
+    wt = torch.from_numpy(w).cuda()
+    a = torch.empty_like(Ut)
+    B.lbm_step_adjoint(s.ctx, Ut, wt, a)
+    lhs, rhs = float(np.sum(jv * w)), float(np.sum(v * a.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(jv) * np.linalg.norm(w), (lhs, rhs)
+    # the theta-supplied adjoint with the face factors of the forward step
+    s.set_state(Ut)
+    gtx, gty = s.step_theta()
+    assert np.array_equal(gtx.cpu().numpy(), tx) and np.array_equal(gty.cpu().numpy(), ty)
+    b = torch.empty_like(Ut)
+    B.lbm_step_adjoint_theta(s.ctx, Ut, gtx, gty, wt, b)
+    assert torch.equal(a, b)
+    s.close()
