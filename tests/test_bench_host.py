@@ -1,0 +1,68 @@
+"""Host-side logic of bench.py, on the CPU: the one-GPU guard, the counter
+record's link to the kernel source, and the measured-traffic lookup."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_source_digest_ignores_comments_only():
+    d = bench.kernel_source_digest()
+    assert len(d) == 64 and d == bench.kernel_source_digest()
+
+
+def _algorithmic():
+    """Algorithmic HBM bytes per launch: 20 state values read and written per
+    cell, 4 bytes each in the float32-state form, 8 in float64."""
+    from paper_2411_15001_amd import cases
+
+    batch_cells = sum(int(n) ** 2 for n in cases.batch_sides(256, seed=0))
+    return {"blast8192_fp32": 8192 ** 2 * 160, "blast8192_fp64": 8192 ** 2 * 320,
+            "rarefaction2048_fp64": 2048 ** 2 * 320, "batch256_fp32": batch_cells * 160}
+
+
+ALGORITHMIC = _algorithmic()
+
+
+def _record():
+    with open(bench.PMC_FILE) as f:
+        return json.load(f)
+
+
+def test_traffic_lookup_matches_launch_shape():
+    rec = _record()
+    if rec.get("source_sha256") != bench.kernel_source_digest():
+        pytest.skip("the step kernel changed since its counters were recorded")
+    if not os.path.exists(os.path.join(ROOT, "paper_2411_15001_amd", "libvlbm.so")):
+        pytest.skip("library not built")
+    for key, entry in rec.items():
+        if not isinstance(entry, dict) or "launch" not in entry:
+            continue
+        launch = entry["launch"]
+        got = bench.traffic_for(key, launch)
+        assert got == entry["bytes_per_launch"], key
+        # the measured bytes lie at most 15% above the algorithmic ones (the
+        # re-read halo rows and columns) and not below them
+        ratio = got / ALGORITHMIC[key]
+        assert 1.0 <= ratio < 1.15, (key, ratio)
+        # another strip height has other halo re-reads: no figure
+        other = [launch[0] * 2] + list(launch[1:])
+        assert bench.traffic_for(key, other) is None
+        # missing trailing launch values read as 0
+        assert bench.traffic_for(key, launch[:2]) == (got if all(v == 0 for v in launch[2:]) else None)
+    assert bench.traffic_for("no_such_workload", [64, 4]) is None
