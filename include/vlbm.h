@@ -215,7 +215,11 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
  * All three are float64 states in the layout above (single instance and
  * LBM_FP64, LBM_ENOTSUP otherwise; ny <= 65535).  Periodic and outflow
  * boundaries and sponge layers: with theta frozen the outflow ghosts only
- * copy the edge cells, whose adjoint takes the copied reads back.  Uses the context's
+ * copy the edge cells, whose adjoint takes the copied reads back.  Boundary
+ * cells of lbm_set_boundary: a wall ghost mirrors its edge cell, whose
+ * adjoint takes the mirrored reads back; Dirichlet ghosts are constants of
+ * the map and contribute nothing, but their states enter lambda^n as in the
+ * forward step, so they must be the states of step n.  Uses the context's
  * workspace as scratch; does not change the context's own state.  Fully
  * asynchronous on the context's stream (no host synchronisation); Ubar_n
  * must not alias U_n or Ubar_np1, and U_n must not be a context buffer. */
@@ -288,7 +292,7 @@ lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
  * side given no state array would be read from NULL).  kind_dev = NULL
  * restores zero-gradient cells on that side.  Walls
  * need two cells along their axis.  Single instance; the adjoint entry points
- * return LBM_ENOTSUP while any side has a description.  Synchronises; drops
+ * cover the described cells (see lbm_step_adjoint).  Synchronises; drops
  * captured graphs. */
 lbm_status lbm_set_boundary(lbm_ctx* ctx, int32_t side, const uint8_t* kind_dev,
                             const double* state_dev);

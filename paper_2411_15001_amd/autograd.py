@@ -1,8 +1,11 @@
 """Reverse-mode differentiation of a rollout of the blended scheme.
 
-`rollout(u0, nsteps, checkpoint_every, **params)` returns the moments
-(rho, m1, m2, E) after `nsteps` steps from the initial moments u0 [4, ny, nx]
-(float64, device) and is differentiable with respect to u0.  The backward
+`rollout(u0, nsteps, checkpoint_every, boundary=None, **params)` returns the
+moments (rho, m1, m2, E) after `nsteps` steps from the initial moments u0
+[4, ny, nx] (float64, device) and is differentiable with respect to u0.
+`boundary` optionally maps a side (0 west, 1 east, 2 south, 3 north) to
+(kinds, states) as in Solver.set_boundary: wall and Dirichlet cells, held for
+the whole rollout (the Dirichlet states are constants of the map).  The backward
 pass holds the blending factors theta^n and the kinetic speeds a^n at the
 values of the forward pass (a fixed active set; with a fixed kinetic speed
 and theta = 1 everywhere this is the exact derivative of the map).
@@ -26,10 +29,12 @@ from .solver import Solver
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, nsteps, k, params):
+    def forward(ctx, u0, nsteps, k, params, boundary):
         s = Solver(u0.detach(), **params)
         if s.params.precision != B.LBM_FP64:
             raise ValueError("the rollout adjoint is float64 only")
+        for side, (kinds, states) in (boundary or {}).items():
+            s.set_boundary(side, kinds, states)
         ckpts = [s.get_state()]
         done = 0
         while done < nsteps:
@@ -78,9 +83,9 @@ class _Rollout(torch.autograd.Function):
         s.close()
         ctx.solver = None
         ctx.ckpts = None
-        return u0bar, None, None, None
+        return u0bar, None, None, None, None
 
 
-def rollout(u0, nsteps, checkpoint_every=20, **params):
+def rollout(u0, nsteps, checkpoint_every=20, boundary=None, **params):
     """Differentiable rollout: moments after nsteps steps, [4, ny, nx]."""
-    return _Rollout.apply(u0, int(nsteps), int(checkpoint_every), params)
+    return _Rollout.apply(u0, int(nsteps), int(checkpoint_every), params, boundary)

@@ -27,6 +27,19 @@
 // (1 + tW) J_{M_1}^T g_1(x) to ubar(x) and -tW g_1(x) to ubar_1(x); likewise
 // M_2 / tE at an east edge, M_3 / tS at a south edge, M_4 / tN at a north
 // edge.
+//
+// Boundary cells described per side (walls and Dirichlet states): a
+// Dirichlet ghost holds given moments and their Maxwellians at the frozen a,
+// so it does not depend on the state and its term drops too.  A wall ghost
+// mirrors the edge cell: its moments are R u(x), with R negating the normal
+// momentum, and its two distributions along the normal are the edge cell's
+// other one, mirrored.  At a west wall u_1'(x) = (1 + tW) M_1(R u_x)
+// - tW R u_2(x), and since the Euler flux satisfies f(R u) = -R f(u) (for an
+// x-mirror; g likewise for a y-mirror), M_1(R u) = R M_2(u): the edge cell's
+// own g_1(x) adds (1 + tW) J_{M_2}^T R g_1(x) to ubar(x) and -tW R g_1(x) to
+// ubar_2(x).  Likewise at an east wall (M_1, slot 1, tE), a south wall (M_4,
+// slot 4, tS) and a north wall (M_3, slot 3, tN).  Streaming reads no
+// diagonal neighbour, so no corner ghost enters the map.
 
 #include "vlbm_internal.h"
 
@@ -73,8 +86,15 @@ __device__ __forceinline__ double kinetic_speed(const Scheme& s, const Slots* sl
   return (s.a_mode == 1) ? s.a_fixed : 2.0 * s.beta * lam / (1.0 - s.alpha);
 }
 
+// Kind of the boundary cell beyond an edge cell: the side's description, or
+// zero-gradient without one.
+__device__ __forceinline__ int edge_kind(const uint8_t* k, int r) {
+  return k ? (int)k[r] : BND_ZERO_GRADIENT;
+}
+
 // EDGES: the context has an outflow axis (the edge terms above); periodic
-// contexts run without them.
+// contexts run without them.  kinds: the boundary descriptions per side
+// (west, east, south, north; NULL: zero-gradient).
 template <bool EDGES>
 __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, int ny, long long P,
                                                            const double* __restrict__ U,
@@ -82,7 +102,8 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
                                                            double* __restrict__ B0,
                                                            const double* __restrict__ tx,
                                                            const double* __restrict__ ty,
-                                                           const Slots* sl, int slot) {
+                                                           const Slots* sl, int slot,
+                                                           BndKinds kinds) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= nx || j >= ny) return;
@@ -99,9 +120,14 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
   const long long cS = (long long)js * nx + i, cN = (long long)jn * nx + i;
   const double tW = tx[(long long)j * (nx + 1) + i], tE = tx[(long long)j * (nx + 1) + i + 1];
   const double tS = ty[(long long)j * nx + i], tN = ty[(long long)(j + 1) * nx + i];
+  // kinds of the ghosts beyond this cell's edges
+  const int kw = gw ? edge_kind(kinds.k[0], j) : -1, ke = ge ? edge_kind(kinds.k[1], j) : -1;
+  const int ks = gs ? edge_kind(kinds.k[2], i) : -1, kn = gn ? edge_kind(kinds.k[3], i) : -1;
   // g1..g4: adjoint reaching u_k' of the neighbour that reads this cell
-  // (0 for a ghost); h1..h4: this cell's own g_k, read back through a ghost
+  // (0 for a ghost); h1..h4: this cell's own g_k, read back through a
+  // zero-gradient ghost; m1..m4: the same through a wall ghost, mirrored
   double u[4], ub[4], g1[4], g2[4], g3[4], g4[4], h1[4], h2[4], h3[4], h4[4];
+  double m1[4], m2[4], m3[4], m4[4];
   for (int c = 0; c < 4; ++c) {
     u[c] = U[c * P + cX];
     ub[c] = B1[c * P + cX];
@@ -109,18 +135,27 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
     g2[c] = gw ? 0.0 : B1[(8 + c) * P + cW] + B1[c * P + cW];
     g3[c] = gn ? 0.0 : B1[(12 + c) * P + cN] + B1[c * P + cN];
     g4[c] = gs ? 0.0 : B1[(16 + c) * P + cS] + B1[c * P + cS];
-    h1[c] = gw ? B1[(4 + c) * P + cX] + ub[c] : 0.0;
-    h2[c] = ge ? B1[(8 + c) * P + cX] + ub[c] : 0.0;
-    h3[c] = gs ? B1[(12 + c) * P + cX] + ub[c] : 0.0;
-    h4[c] = gn ? B1[(16 + c) * P + cX] + ub[c] : 0.0;
+    const double o1 = (kw >= 0 && kw != BND_DIRICHLET) ? B1[(4 + c) * P + cX] + ub[c] : 0.0;
+    const double o2 = (ke >= 0 && ke != BND_DIRICHLET) ? B1[(8 + c) * P + cX] + ub[c] : 0.0;
+    const double o3 = (ks >= 0 && ks != BND_DIRICHLET) ? B1[(12 + c) * P + cX] + ub[c] : 0.0;
+    const double o4 = (kn >= 0 && kn != BND_DIRICHLET) ? B1[(16 + c) * P + cX] + ub[c] : 0.0;
+    h1[c] = kw == BND_ZERO_GRADIENT ? o1 : 0.0;
+    h2[c] = ke == BND_ZERO_GRADIENT ? o2 : 0.0;
+    h3[c] = ks == BND_ZERO_GRADIENT ? o3 : 0.0;
+    h4[c] = kn == BND_ZERO_GRADIENT ? o4 : 0.0;
+    // R: the x-mirror negates m_1, the y-mirror m_2
+    m1[c] = kw == BND_WALL ? (c == 1 ? -o1 : o1) : 0.0;
+    m2[c] = ke == BND_WALL ? (c == 1 ? -o2 : o2) : 0.0;
+    m3[c] = ks == BND_WALL ? (c == 2 ? -o3 : o3) : 0.0;
+    m4[c] = kn == BND_WALL ? (c == 2 ? -o4 : o4) : 0.0;
   }
   const Jac J = jac_of(u, sc.gamma);
   double z1[4], z2[4], z3[4], z4[4];
   for (int c = 0; c < 4; ++c) {
-    z1[c] = (1.0 + tE) * g1[c] - tE * ub[c] + (1.0 + tW) * h1[c];
-    z2[c] = (1.0 + tW) * g2[c] - tW * ub[c] + (1.0 + tE) * h2[c];
-    z3[c] = (1.0 + tN) * g3[c] - tN * ub[c] + (1.0 + tS) * h3[c];
-    z4[c] = (1.0 + tS) * g4[c] - tS * ub[c] + (1.0 + tN) * h4[c];
+    z1[c] = (1.0 + tE) * g1[c] - tE * ub[c] + (1.0 + tW) * h1[c] + (1.0 + tE) * m2[c];
+    z2[c] = (1.0 + tW) * g2[c] - tW * ub[c] + (1.0 + tE) * h2[c] + (1.0 + tW) * m1[c];
+    z3[c] = (1.0 + tN) * g3[c] - tN * ub[c] + (1.0 + tS) * h3[c] + (1.0 + tN) * m4[c];
+    z4[c] = (1.0 + tS) * g4[c] - tS * ub[c] + (1.0 + tN) * h4[c] + (1.0 + tS) * m3[c];
   }
   double dx[4], dy[4], ax[4], by[4];
   for (int c = 0; c < 4; ++c) {
@@ -131,10 +166,10 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(Scheme sc, int nx, in
   Bt(J, dy, by);
   for (int c = 0; c < 4; ++c) {
     B0[c * P + cX] = sc.alpha * ub[c] + w * (z1[c] + z2[c] + z3[c] + z4[c]) + r2a * (ax[c] + by[c]);
-    B0[(4 + c) * P + cX] = tE * (ub[c] - g1[c]) - tW * h1[c];
-    B0[(8 + c) * P + cX] = tW * (ub[c] - g2[c]) - tE * h2[c];
-    B0[(12 + c) * P + cX] = tN * (ub[c] - g3[c]) - tS * h3[c];
-    B0[(16 + c) * P + cX] = tS * (ub[c] - g4[c]) - tN * h4[c];
+    B0[(4 + c) * P + cX] = tE * (ub[c] - g1[c]) - tW * h1[c] - tE * m2[c];
+    B0[(8 + c) * P + cX] = tW * (ub[c] - g2[c]) - tE * h2[c] - tW * m1[c];
+    B0[(12 + c) * P + cX] = tN * (ub[c] - g3[c]) - tS * h3[c] - tN * m4[c];
+    B0[(16 + c) * P + cX] = tS * (ub[c] - g4[c]) - tN * h4[c] - tS * m3[c];
   }
 }
 
@@ -170,15 +205,15 @@ __global__ __launch_bounds__(256) void adjoint_init_kernel(Scheme sc, long long 
 
 hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane, const double* U,
                                const double* Ub1, double* Ub0, const double* tx, const double* ty,
-                               const Slots* slots, int slot, hipStream_t s) {
+                               const Slots* slots, int slot, const BndKinds& kinds, hipStream_t s) {
   const dim3 block(256);
   const dim3 grid((in.nx + 255) / 256, in.ny);
   if (sc.bc_x == 1 || sc.bc_y == 1)
     hipLaunchKernelGGL(adjoint_step_kernel<true>, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1,
-                       Ub0, tx, ty, slots, slot);
+                       Ub0, tx, ty, slots, slot, kinds);
   else
     hipLaunchKernelGGL(adjoint_step_kernel<false>, grid, block, 0, s, sc, in.nx, in.ny, plane, U, Ub1,
-                       Ub0, tx, ty, slots, slot);
+                       Ub0, tx, ty, slots, slot, kinds);
   return hipGetLastError();
 }
 

@@ -974,13 +974,17 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
-  if (c->has_bnd) return fail(c, LBM_ENOTSUP, "the adjoint does not cover wall or Dirichlet boundary cells");
   if (!U || !Ub1 || !Ub0) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())
     return fail(c, LBM_EINVAL, "U_n must not be one of the context's own state buffers");
   if (c->insts[0].ny > 65535) return fail(c, LBM_ENOTSUP, "the adjoint supports ny <= 65535");
   return LBM_OK;
+}
+vlbm::BndKinds bnd_kinds(const lbm_ctx* c) {
+  vlbm::BndKinds k;
+  for (int s = 0; s < 4; ++s) k.k[s] = c->bnd_kind[s];
+  return k;
 }
 }  // namespace
 
@@ -1000,10 +1004,13 @@ extern "C" lbm_status lbm_step_adjoint_theta(lbm_ctx* c, const double* U, const 
     if (e == hipSuccess)
       e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, c->plane, U, c->slots, scratch,
                                     LBM_FP64, c->stream);
+    // the forward step's lambda^n also covers the Dirichlet states
+    if (e == hipSuccess && c->has_dirichlet)
+      e = vlbm::launch_bnd_lambda(make_args(c, U, nullptr, scratch), c->insts[0], scratch, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
   }
   e = vlbm::launch_adjoint_step(c->sc, c->insts[0], c->plane, U, Ub1, Ub0, tx, ty, c->slots,
-                                scratch, c->stream);
+                                scratch, bnd_kinds(c), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   return LBM_OK;
 }
@@ -1033,10 +1040,11 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double
   vlbm::StepArgs a = make_args(c, U, c->other(), scratch);
   a.theta_x = tx;
   a.theta_y = ty;
-  e = vlbm::launch_step(a, LBM_FP64, c->stream);
+  // (lambda^n raised by the Dirichlet states first, as in the forward step)
+  e = launch_step_with_bnd(c, a);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint theta");
   e = vlbm::launch_adjoint_step(c->sc, in, c->plane, U, Ub1, Ub0, tx, ty, c->slots, scratch,
-                                c->stream);
+                                bnd_kinds(c), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
   // restore the scalar slots (lambda, t, counters) of the forward run
   e = hipMemcpyAsync(c->slots, save, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
@@ -1049,7 +1057,6 @@ extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const doubl
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
-  if (c->has_bnd) return fail(c, LBM_ENOTSUP, "the adjoint does not cover wall or Dirichlet boundary cells");
   if (!u0 || !Ub0 || !u0b) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   Slots* save = (Slots*)(c->ws + c->lay.slots_save);
   hipError_t e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);

@@ -78,11 +78,16 @@ hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStre
 // states of a single instance (one workgroup).
 hipError_t launch_bnd_lambda(const StepArgs& a, const Inst& in, int slot, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s);
-// Adjoint (adjoint.hip).
+// Adjoint (adjoint.hip).  Boundary kinds per side (west, east, south,
+// north), uint8 device arrays as in StepArgs; NULL: zero-gradient.
+struct BndKinds {
+  const uint8_t* k[4];
+};
 hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane,
                                const double* U, const double* Ubar1, double* Ubar0,
                                const double* theta_x, const double* theta_y,
-                               const Slots* slot_src, int slot, hipStream_t s);
+                               const Slots* slot_src, int slot, const BndKinds& kinds,
+                               hipStream_t s);
 hipError_t launch_adjoint_init(const Scheme& sc, const Inst& in, const double* u0,
                                const double* Ubar0, double* u0bar,
                                const Slots* slots, int slot, hipStream_t s);
