@@ -208,7 +208,7 @@ def test_batch_sweep_case(i, gpu):
     bs.close()
 
 
-N_ADJOINT_CASES = 24
+N_ADJOINT_CASES = 48
 
 
 def draw_adjoint_case(i):
@@ -225,6 +225,12 @@ def draw_adjoint_case(i):
     c["beta"] = float(rng.choice([1.0, 1.1, 2.0]))
     c["steps"] = int(rng.integers(1, 10))
     c["seed"] = int(rng.integers(0, 1 << 30))
+    c["rlmp"] = (0.999, 1.001)
+    c["fixed_a"] = False
+    c["bnd"] = [None] * 4
+    for side in range(4):
+        if (c["bc_x"] if side < 2 else c["bc_y"]) and c["sponge"] == 0 and rng.random() < 0.5:
+            c["bnd"][side] = str(rng.choice(["z", "w", "d", "m"]))
     return c
 
 
@@ -234,23 +240,20 @@ def test_adjoint_sweep_case(i, gpu):
     frozen at the forward values) equals <v, J^T w> from lbm_step_adjoint to
     1e-12, and lbm_step_adjoint_theta with the face factors of lbm_step_theta
     equals lbm_step_adjoint bit for bit, over random sizes, limiter sets,
-    orders, axes, sponges, alpha and beta."""
+    orders, axes, sponges, alpha, beta and wall / Dirichlet cells."""
     torch = gpu
     c = draw_adjoint_case(i)
     print("adjoint sweep case", i, c, flush=True)
-    nx, ny = c["nx"], c["ny"]
-    if c["lims"] == 0 and c["order"] == 2:
-        u0 = cases.gaussian_bump(max(nx, ny), seed=c["seed"] % 7, amp=0.2, sigma=0.2)
-    else:
-        u0 = cases.riemann4(max(nx, ny), seed=c["seed"] % 97)
-    u0 = np.ascontiguousarray(u0[:, :ny, :nx])
-    kw = dict(dx=1.0 / max(nx, ny), limiters=c["lims"], order=c["order"], alpha=c["alpha"],
+    u0, cfg, kinds, states = build(c)
+    kw = dict(dx=cfg.params().dx, limiters=c["lims"], order=c["order"], alpha=c["alpha"],
               a_beta=c["beta"], bc_x=c["bc_x"], bc_y=c["bc_y"], sponge=c["sponge"])
-    cfg = oracle.Config(nx=nx, ny=ny, **kw)
     S, _ = oracle.init(cfg, u0)
     S, _, _, tot = oracle.run(cfg, S, c["steps"])
     _, tx, ty, info = oracle.step(cfg, S)
     s = Solver(u0, **kw)
+    for side in range(4):
+        if kinds[side] is not None:
+            s.set_boundary(side, kinds[side], states[side])
     Ut = torch.from_numpy(S).cuda()
     rng = np.random.default_rng(c["seed"])
     v = rng.normal(size=S.shape)
