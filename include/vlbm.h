@@ -281,7 +281,10 @@ lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
  * exchanged) or LBM_BND_DIRICHLET (2: the ghost layers hold the moments given
  * in state_dev with their Maxwellians at the current a^n, Section 4.8).
  * state_dev: float64 [4][len] device array of (rho, m1, m2, E) per cell, read
- * where the kind is Dirichlet (may be NULL without Dirichlet cells).  A ghost
+ * where the kind is Dirichlet (may be NULL without Dirichlet cells); those
+ * states must be admissible (rho > 0, p > 0, finite: LBM_EINVAL otherwise,
+ * checked here; a state the caller makes non-admissible later is skipped by
+ * lambda^n, and the step's results are then unspecified).  A ghost
  * beyond a corner takes the x-side rule first, then the y-side rule.  Each
  * step first raises lambda^n by the Dirichlet states, so that a^n satisfies
  * Bouchut's condition for every state the stencil reads.  The caller owns

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <string>
 #include <tuple>
@@ -742,6 +743,22 @@ lbm_status lbm_set_boundary(lbm_ctx* c, int32_t side, const uint8_t* kind, const
       dirichlet |= h[r] == vlbm::BND_DIRICHLET;
     }
     if (dirichlet && !state) return fail(c, LBM_EINVAL, "Dirichlet cells need a state array");
+    if (dirichlet) {
+      // the Dirichlet states must be admissible (rho > 0, p > 0, finite)
+      std::vector<double> st((size_t)4 * len);
+      e = hipMemcpyAsync(st.data(), state, st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "reading boundary states");
+      const double gm1 = c->p.gamma - 1.0;
+      for (int r = 0; r < len; ++r) {
+        if (h[r] != vlbm::BND_DIRICHLET) continue;
+        const double rho = st[r], m1 = st[(size_t)len + r], m2 = st[2 * (size_t)len + r],
+                     E = st[3 * (size_t)len + r];
+        const double p = gm1 * (E - 0.5 * (m1 * m1 + m2 * m2) / rho);
+        if (!(rho > 0.0) || !(p > 0.0) || !std::isfinite(E) || !std::isfinite(m1) || !std::isfinite(m2))
+          return fail(c, LBM_EINVAL, "a Dirichlet state is not admissible (rho > 0, p > 0, finite)");
+      }
+    }
   }
   c->bnd_kind[side] = kind;
   c->bnd_state[side] = kind ? state : nullptr;

@@ -192,6 +192,21 @@ def test_boundary_errors(gpu):
         assert e.value.status == B.LBM_EINVAL
     with pytest.raises(ValueError):
         s.set_boundary(N, np.ones(31, np.uint8))
+    # Dirichlet states must be admissible: negative density, negative
+    # pressure, a non-finite value
+    good = np.repeat(prim(1.0, 0.1, 0.0, 1.0)[:, None], 32, 1)
+    for bad in (prim(-1.0, 0.0, 0.0, 1.0), prim(1.0, 0.0, 0.0, -0.5), np.array([1.0, np.inf, 0.0, 3.0])):
+        st = good.copy()
+        st[:, 7] = bad
+        with pytest.raises(B.LbmError) as e:
+            s.set_boundary(S_, np.full(32, 2, np.uint8), np.ascontiguousarray(st))
+        assert e.value.status == B.LBM_EINVAL
+    # a non-admissible state where the kind is not Dirichlet is not read
+    st = good.copy()
+    st[:, 7] = prim(-1.0, 0.0, 0.0, 1.0)
+    k = np.full(32, 2, np.uint8)
+    k[7] = 1
+    s.set_boundary(S_, k, np.ascontiguousarray(st))
     s.close()
 
 
