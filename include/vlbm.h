@@ -294,11 +294,20 @@ lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
  * after changing them (a kind turned Dirichlet behind the library's back on a
  * side given no state array would be read from NULL).  kind_dev = NULL
  * restores zero-gradient cells on that side.  Walls
- * need two cells along their axis.  Single instance; the adjoint entry points
- * cover the described cells (see lbm_step_adjoint).  Synchronises; drops
+ * need two cells along their axis.  Single-instance contexts (ensembles:
+ * lbm_set_instance_boundary); the adjoint entry points cover the described
+ * cells (see lbm_step_adjoint).  Synchronises; drops
  * captured graphs. */
 lbm_status lbm_set_boundary(lbm_ctx* ctx, int32_t side, const uint8_t* kind_dev,
                             const double* state_dev);
+
+/* The same description for instance inst of an ensemble (lbm_init_batch;
+ * inst 0 of a single-instance context): arrays sized by that instance's
+ * sides, the same checks and rules; each instance's Dirichlet states raise
+ * only that instance's lambda^n.  lbm_set_boundary on an ensemble returns
+ * LBM_ENOTSUP.  Synchronises; drops captured graphs. */
+lbm_status lbm_set_instance_boundary(lbm_ctx* ctx, int32_t inst, int32_t side,
+                                     const uint8_t* kind_dev, const double* state_dev);
 
 /* Grid of the step kernel.  groups_per_cu = 0 (the default) launches one wave
  * per strip; k in [1, 32] launches a persistent grid of at most k workgroups

@@ -44,6 +44,7 @@ EXPORTS = [
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_between", "lbm_step_adjoint",
     "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
     "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode", "lbm_set_boundary",
+    "lbm_set_instance_boundary",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -117,6 +118,7 @@ def lib():
         L.lbm_set_grid.argtypes = [vp, i32]
         L.lbm_set_strip_mode.argtypes = [vp, i32]
         L.lbm_set_boundary.argtypes = [vp, i32, vp, vp]
+        L.lbm_set_instance_boundary.argtypes = [vp, i32, i32, vp, vp]
         L.lbm_get_strip_mode.argtypes = [vp, i32p]
         L.lbm_get_grid.argtypes = [vp, i32p, i32p]
         L.lbm_status_string.argtypes = [ctypes.c_int]
@@ -383,14 +385,10 @@ def lbm_set_strip_mode(ctx, mode=0):
     return _check(lib().lbm_set_strip_mode(ctx, int(mode)), ctx)
 
 
-def lbm_set_boundary(ctx, side, kind=None, state=None):
-    """Boundary cells of one side (0 west, 1 east, 2 south, 3 north): kind a
-    uint8 device tensor of the side's length (LBM_BND_*), state float64
-    [4, len] device tensor of Dirichlet moments (or None); kind None restores
-    zero-gradient cells.  The tensors must outlive the context's steps."""
+def _boundary_ptrs(ctx, inst, side, kind, state):
     import torch
 
-    nx, ny = _inst_shape(ctx)
+    nx, ny = _inst_shape(ctx, int(inst))
     n = ny if int(side) in (0, 1) else nx
     kp = sp = None
     if kind is not None:
@@ -399,7 +397,22 @@ def lbm_set_boundary(ctx, side, kind=None, state=None):
         if state is not None:
             _require_cuda(state, torch.float64, 4 * n, "state")
             sp = _ptr(state)
+    return kp, sp
+
+
+def lbm_set_boundary(ctx, side, kind=None, state=None):
+    """Boundary cells of one side (0 west, 1 east, 2 south, 3 north): kind a
+    uint8 device tensor of the side's length (LBM_BND_*), state float64
+    [4, len] device tensor of Dirichlet moments (or None); kind None restores
+    zero-gradient cells.  The tensors must outlive the context's steps."""
+    kp, sp = _boundary_ptrs(ctx, 0, side, kind, state)
     return _check(lib().lbm_set_boundary(ctx, int(side), kp, sp), ctx)
+
+
+def lbm_set_instance_boundary(ctx, inst, side, kind=None, state=None):
+    """lbm_set_boundary for instance `inst` of an ensemble."""
+    kp, sp = _boundary_ptrs(ctx, inst, side, kind, state)
+    return _check(lib().lbm_set_instance_boundary(ctx, int(inst), int(side), kp, sp), ctx)
 
 
 def lbm_get_strip_mode(ctx):

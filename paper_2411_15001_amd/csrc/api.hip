@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <string>
@@ -92,7 +93,7 @@ Scheme make_scheme(const lbm_params* p) {
 }
 
 struct Layout {
-  size_t slots, slots_save, red, insts, items, bufA, bufB, theta, total;
+  size_t slots, slots_save, red, insts, items, bndt, bufA, bufB, theta, total;
 };
 
 Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
@@ -114,6 +115,8 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   o = align_up(o + sizeof(Inst) * (size_t)n);
   L.items = o;
   o = align_up(o + sizeof(int) * (size_t)(n > 1 ? items : 0));
+  L.bndt = o;  // boundary descriptions of an ensemble's instances
+  o = align_up(o + sizeof(vlbm::BndDesc) * (size_t)(n > 1 ? n : 0));
   L.bufA = o;
   o = align_up(o + (size_t)20 * cells * elem);
   L.bufB = o;
@@ -150,9 +153,11 @@ struct lbm_ctx {
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
   int n_cu = 256;       // compute units of the context's device
   bool detached = false;  // the current state lives in a caller buffer (lbm_step_between)
-  const uint8_t* bnd_kind[4] = {};  // lbm_set_boundary (device arrays, caller-owned)
-  const double* bnd_state[4] = {};
-  bool side_dirichlet[4] = {};
+  // boundary descriptions per instance (caller-owned device arrays; copied
+  // to the workspace table for ensembles); per instance and side: any
+  // Dirichlet cell
+  std::vector<vlbm::BndDesc> bnd;
+  std::vector<std::array<bool, 4>> side_dirichlet;
   bool has_bnd = false, has_dirichlet = false;
   std::string err;
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
@@ -296,10 +301,10 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
   a.xcd_remap = c->xcd;
   a.groups = compute_groups(c);
   a.sc = c->sc;
-  for (int k = 0; k < 4; ++k) {
-    a.bnd_kind[k] = c->bnd_kind[k];
-    a.bnd_state[k] = c->bnd_state[k];
-  }
+  if (c->n_inst > 1)
+    a.bnd_table = (const vlbm::BndDesc*)(c->ws + c->lay.bndt);
+  else if (!c->bnd.empty())
+    a.bnd1 = c->bnd[0];
   a.bnd = c->has_bnd ? 1 : 0;
   return a;
 }
@@ -308,7 +313,7 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
 // (Bouchut's condition covers every state the stencil reads).
 hipError_t launch_step_with_bnd(const lbm_ctx* c, const vlbm::StepArgs& a) {
   if (c->has_dirichlet) {
-    hipError_t e = vlbm::launch_bnd_lambda(a, c->insts[0], a.slot, c->stream);
+    hipError_t e = vlbm::launch_bnd_lambda(a, a.slot, c->stream);
     if (e != hipSuccess) return e;
   }
   return vlbm::launch_step(a, c->p.precision, c->stream);
@@ -722,14 +727,15 @@ lbm_status lbm_set_strip_mode(lbm_ctx* c, int32_t mode) {
   return rebuild_launch(c);
 }
 
-lbm_status lbm_set_boundary(lbm_ctx* c, int32_t side, const uint8_t* kind, const double* state) {
+lbm_status lbm_set_instance_boundary(lbm_ctx* c, int32_t inst, int32_t side, const uint8_t* kind,
+                                     const double* state) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
   if (side < 0 || side > 3) return fail(c, LBM_EINVAL, "side must be 0 (west), 1 (east), 2 (south) or 3 (north)");
-  if (c->n_inst != 1) return fail(c, LBM_ENOTSUP, "boundary descriptions are single-instance only");
   const int ax = side / 2;
   if ((ax == 0 ? c->p.bc_x : c->p.bc_y) != LBM_BC_OUTFLOW)
     return fail(c, LBM_EINVAL, "boundary descriptions need the side's axis to be non-periodic (LBM_BC_OUTFLOW)");
-  const Inst& in = c->insts[0];
+  const Inst& in = c->insts[inst];
   const int len = ax == 0 ? in.ny : in.nx, n = ax == 0 ? in.nx : in.ny;
   bool dirichlet = false;
   if (kind) {
@@ -760,18 +766,36 @@ lbm_status lbm_set_boundary(lbm_ctx* c, int32_t side, const uint8_t* kind, const
       }
     }
   }
-  c->bnd_kind[side] = kind;
-  c->bnd_state[side] = kind ? state : nullptr;
-  c->side_dirichlet[side] = dirichlet;
+  if (c->bnd.size() != (size_t)c->n_inst) {
+    c->bnd.assign(c->n_inst, vlbm::BndDesc{});
+    c->side_dirichlet.assign(c->n_inst, {false, false, false, false});
+  }
+  c->bnd[inst].kind[side] = kind;
+  c->bnd[inst].state[side] = kind ? state : nullptr;
+  c->side_dirichlet[inst][side] = dirichlet;
   c->has_bnd = false;
   c->has_dirichlet = false;
-  for (int k = 0; k < 4; ++k) {
-    c->has_bnd |= c->bnd_kind[k] != nullptr;
-    c->has_dirichlet |= c->side_dirichlet[k];
-  }
+  for (int i = 0; i < c->n_inst; ++i)
+    for (int k = 0; k < 4; ++k) {
+      c->has_bnd |= c->bnd[i].kind[k] != nullptr;
+      c->has_dirichlet |= c->side_dirichlet[i][k];
+    }
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+  if (c->n_inst > 1) {  // ensembles read the descriptions from the workspace table
+    hipError_t e = hipMemcpyAsync(c->ws + c->lay.bndt, c->bnd.data(), sizeof(vlbm::BndDesc) * c->n_inst,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading boundary descriptions");
+  }
   return LBM_OK;
+}
+
+lbm_status lbm_set_boundary(lbm_ctx* c, int32_t side, const uint8_t* kind, const double* state) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->n_inst != 1)
+    return fail(c, LBM_ENOTSUP, "ensembles describe boundaries per instance (lbm_set_instance_boundary)");
+  return lbm_set_instance_boundary(c, 0, side, kind, state);
 }
 
 lbm_status lbm_get_strip_mode(const lbm_ctx* c, int32_t* mode) {
@@ -1000,7 +1024,7 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
 }
 vlbm::BndKinds bnd_kinds(const lbm_ctx* c) {
   vlbm::BndKinds k;
-  for (int s = 0; s < 4; ++s) k.k[s] = c->bnd_kind[s];
+  for (int s = 0; s < 4; ++s) k.k[s] = c->bnd.empty() ? nullptr : c->bnd[0].kind[s];
   return k;
 }
 }  // namespace
@@ -1023,7 +1047,7 @@ extern "C" lbm_status lbm_step_adjoint_theta(lbm_ctx* c, const double* U, const 
                                     LBM_FP64, c->stream);
     // the forward step's lambda^n also covers the Dirichlet states
     if (e == hipSuccess && c->has_dirichlet)
-      e = vlbm::launch_bnd_lambda(make_args(c, U, nullptr, scratch), c->insts[0], scratch, c->stream);
+      e = vlbm::launch_bnd_lambda(make_args(c, U, nullptr, scratch), scratch, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
   }
   e = vlbm::launch_adjoint_step(c->sc, c->insts[0], c->plane, U, Ub1, Ub0, tx, ty, c->slots,

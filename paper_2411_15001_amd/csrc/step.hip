@@ -326,9 +326,14 @@ __device__ __forceinline__ void reflect_slots(T s[20], int ax) {
   }
 }
 
+// Boundary description of the instance whose slots are sl.
+__device__ __forceinline__ BndDesc bnd_desc(const StepArgs& A, const Slots* sl) {
+  return A.n_inst > 1 ? A.bnd_table[sl - A.slots] : A.bnd1;
+}
+
 template <class T, class C>
-__device__ void bnd_cell(const StepArgs& A, const Inst& in, const T* __restrict__ sbase, long long P,
-                         int i, int j, const StepConst<T, C>& K, T out[20]) {
+__device__ void bnd_cell(const StepArgs& A, const BndDesc& bd, const Inst& in, const T* __restrict__ sbase,
+                         long long P, int i, int j, const StepConst<T, C>& K, T out[20]) {
   const Scheme& sc = A.sc;
   const int nx = in.nx, ny = in.ny;
   bool refl_x = false, refl_y = false;
@@ -343,9 +348,9 @@ __device__ void bnd_cell(const StepArgs& A, const Inst& in, const T* __restrict_
     const int side = 2 * ax + (idx < 0 ? 0 : 1);
     const int other = ax == 0 ? map_index(j, ny, sc.bc_y) : i;
     const int len = ax == 0 ? ny : nx;
-    const int kind = A.bnd_kind[side] ? (int)A.bnd_kind[side][other] : BND_ZERO_GRADIENT;
+    const int kind = bd.kind[side] ? (int)bd.kind[side][other] : BND_ZERO_GRADIENT;
     if (kind == BND_DIRICHLET) {
-      const double* st = A.bnd_state[side];
+      const double* st = bd.state[side];
       C u[4], f[4], g[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) u[c] = (C)st[(long long)c * len + other];
@@ -428,9 +433,11 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   T raw[20], hraw[8];
   // with boundary descriptions, ghost rows, columns past the edge and the
   // halo columns come from bnd_cell
+  BndDesc bd{};
+  if constexpr (BND) bd = bnd_desc(A, sl);
   auto bnd_load = [&](const int R) {
     if (R < 0 || R >= ny || !lane_out) {
-      bnd_cell<T, C>(A, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
+      bnd_cell<T, C>(A, bd, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
     } else {
       const unsigned o = (unsigned)R * unx + (unsigned)ci;
 #pragma unroll
@@ -438,7 +445,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     }
     if (first || last) {
       T h[20];
-      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
+      bnd_cell<T, C>(A, bd, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         hraw[q] = h[q];
@@ -718,9 +725,11 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   T raw[20], hraw[8] = {}, oraw[2] = {};
   // with boundary descriptions, ghost rows, columns past the edge and the
   // halo columns come from bnd_cell
+  BndDesc bd{};
+  if constexpr (BND) bd = bnd_desc(A, sl);
   auto bnd_load = [&](const int R) {
     if (R < 0 || R >= ny || !lane_out) {
-      bnd_cell<T, C>(A, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
+      bnd_cell<T, C>(A, bd, in, sbase, P, gi < nx + 1 ? gi : nx + 1, R, K, raw);
     } else {
       const unsigned o = (unsigned)R * unx + (unsigned)ci;
 #pragma unroll
@@ -728,13 +737,13 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
     }
     if (first || last) {
       T h[20];
-      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
+      bnd_cell<T, C>(A, bd, in, sbase, P, first ? x0 - 1 : min(x0 + 64, nx + 1), R, K, h);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         hraw[q] = h[q];
         hraw[4 + q] = first ? h[4 + q] : h[8 + q];
       }
-      bnd_cell<T, C>(A, in, sbase, P, first ? x0 - 2 : min(x0 + 65, nx + 1), R, K, h);
+      bnd_cell<T, C>(A, bd, in, sbase, P, first ? x0 - 2 : min(x0 + 65, nx + 1), R, K, h);
       oraw[0] = h[0];
       oraw[1] = h[1];
     }
@@ -1210,13 +1219,15 @@ int grid_for_reduce(long long n) { return grid_for(n, 1024); }
 namespace {
 // Largest wavespeed of the Dirichlet boundary states of one instance, merged
 // into slot `slot` (one workgroup striding over the four sides).
-__global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int nx, int ny, int slot) {
+__global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int slot) {
+  const Inst in = A.n_inst == 1 ? A.inst0 : A.insts[blockIdx.x];
+  const BndDesc bd = bnd_desc(A, A.slots + blockIdx.x);
   double lmax = 0.0;
   for (int side = 0; side < 4; ++side) {
-    const uint8_t* k = A.bnd_kind[side];
+    const uint8_t* k = bd.kind[side];
     if (!k) continue;
-    const int len = side < 2 ? ny : nx;
-    const double* st = A.bnd_state[side];
+    const int len = side < 2 ? in.ny : in.nx;
+    const double* st = bd.state[side];
     for (int r = threadIdx.x; r < len; r += blockDim.x) {
       if (k[r] != BND_DIRICHLET) continue;
       const double l = cell_wavespeed(st[r], st[(long long)len + r], st[2LL * len + r],
@@ -1226,7 +1237,7 @@ __global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int nx, int
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
-  if ((threadIdx.x & 63) == 0 && lmax > 0.0) raise_lambda(&A.slots[0].lam[slot], lmax);
+  if ((threadIdx.x & 63) == 0 && lmax > 0.0) raise_lambda(&A.slots[blockIdx.x].lam[slot], lmax);
 }
 }  // namespace
 
@@ -1250,8 +1261,8 @@ static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, h
     hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false, false>), grid, block, 0, s, a);
 }
 
-hipError_t launch_bnd_lambda(const StepArgs& a, const Inst& in, int slot, hipStream_t s) {
-  hipLaunchKernelGGL(bnd_lambda_kernel, dim3(1), dim3(256), 0, s, a, in.nx, in.ny, slot);
+hipError_t launch_bnd_lambda(const StepArgs& a, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(bnd_lambda_kernel, dim3((unsigned)a.n_inst), dim3(256), 0, s, a, slot);
   return hipGetLastError();
 }
 

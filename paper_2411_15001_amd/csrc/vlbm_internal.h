@@ -23,6 +23,14 @@ struct Inst {
   int pad_;
 };
 
+// Boundary description of one instance: per-cell kinds and Dirichlet moments
+// of the four sides (west, east, south, north; null: zero-gradient), see
+// lbm_set_boundary.
+struct BndDesc {
+  const uint8_t* kind[4];
+  const double* state[4];
+};
+
 // Per-instance device scalars.  lam and t rotate over three slots: step n
 // reads slot n % 3, writes slot (n + 1) % 3 and clears slot (n + 2) % 3.
 struct alignas(128) Slots {
@@ -49,11 +57,13 @@ struct StepArgs {
   int groups;             // launched workgroups
   double* theta_x;        // optional face output (single instance)
   double* theta_y;
-  // per-cell boundary kinds and Dirichlet moments of the four sides (west,
-  // east, south, north; single instance; null: zero-gradient), see lbm_set_boundary
-  const uint8_t* bnd_kind[4];
-  const double* bnd_state[4];
-  int bnd;                // 1 if any side has a boundary description
+  // boundary descriptions: a single instance's in bnd1, an ensemble's in the
+  // device table bnd_table (one entry per instance)
+  union {
+    BndDesc bnd1;
+    const BndDesc* bnd_table;
+  };
+  int bnd;                // 1 if any instance has a boundary description
   Scheme sc;
 };
 
@@ -74,9 +84,9 @@ hipError_t launch_moments(const Inst& in, long long plane, const void* S,
 hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
                          int blocks, int precision, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
-// Raises slots->lam[slot] to the largest wavespeed of the Dirichlet boundary
-// states of a single instance (one workgroup).
-hipError_t launch_bnd_lambda(const StepArgs& a, const Inst& in, int slot, hipStream_t s);
+// Raises each instance's lam[slot] to the largest wavespeed of its Dirichlet
+// boundary states (one workgroup per instance).
+hipError_t launch_bnd_lambda(const StepArgs& a, int slot, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, long long n, hipStream_t s);
 // Adjoint (adjoint.hip).  Boundary kinds per side (west, east, south,
 // north), uint8 device arrays as in StepArgs; NULL: zero-gradient.

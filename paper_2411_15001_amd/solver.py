@@ -108,11 +108,11 @@ class Solver:
             return
         if isinstance(kind, np.ndarray):
             kind = torch.from_numpy(np.ascontiguousarray(kind, dtype=np.uint8)).cuda()
-        k = kind
+        k = kind.contiguous()  # the library keeps the pointer: hold this tensor
         st = None
         if state is not None:
             st = _as_device(state, torch).contiguous()
-        B.lbm_set_boundary(self.ctx, side, k.contiguous(), st)
+        B.lbm_set_boundary(self.ctx, side, k, st)
         self.boundary[side] = (k, st)
 
     def close(self):
@@ -194,6 +194,25 @@ class BatchSolver:
         """(strip rows, waves per workgroup, groups per CU (0 = one wave per
         strip), strip mode (1 = heights matched to each instance))"""
         return B.lbm_get_launch(self.ctx) + (B.lbm_get_grid(self.ctx)[0], B.lbm_get_strip_mode(self.ctx))
+
+    def set_boundary(self, inst, side, kind=None, state=None):
+        """Boundary cells of one side of instance `inst` (as Solver.set_boundary,
+        sized by that instance); the device copies are kept in
+        self.boundary[(inst, side)]."""
+        import torch
+
+        if not hasattr(self, "boundary"):
+            self.boundary = {}
+        if kind is None:
+            B.lbm_set_instance_boundary(self.ctx, inst, side)
+            self.boundary.pop((inst, side), None)
+            return
+        if isinstance(kind, np.ndarray):
+            kind = torch.from_numpy(np.ascontiguousarray(kind, dtype=np.uint8)).cuda()
+        k = kind.contiguous()
+        st = None if state is None else _as_device(state, torch).contiguous()
+        B.lbm_set_instance_boundary(self.ctx, inst, side, k, st)
+        self.boundary[(inst, side)] = (k, st)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -371,3 +371,51 @@ def test_rollout_gradient_with_walls_and_dirichlet_cells(gpu):
     jvp = float(np.sum(wgt * Sim[0] / h))
     assert limited > 0
     assert abs(float(np.sum(g * d)) - jvp) <= 1e-9 * abs(jvp), (float(np.sum(g * d)), jvp)
+
+
+@pytest.mark.parametrize("prec,lims", [(B.LBM_FP64, 1 | 2 | 8), (B.LBM_FP64, 4 | 8), (B.LBM_FP32_STATE, 1 | 8)])
+def test_ensemble_boundaries_equal_single_runs(prec, lims, gpu):
+    """Per-instance wall and Dirichlet cells in an uneven ensemble (one launch
+    per step, then graph replays): every instance bit-identical to the same
+    instance run alone with the same boundary cells, and (float64) to the
+    oracle; each instance's Dirichlet states raise only its own lambda."""
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    sizes = [(100, 70), (64, 64), (130, 45), (40, 3), (2, 30), (77, 90)]
+    patterns = ["wdwm", None, "ddmm", "mdww", "wwdm", "zdwd"]
+    rng = np.random.default_rng(17)
+    u0s, descs = [], []
+    for i, ((nx, ny), pat) in enumerate(zip(sizes, patterns)):
+        u0s.append(np.ascontiguousarray(cases.riemann4(max(nx, ny), seed=30 + i)[:, :ny, :nx]))
+        descs.append(sides_for(pat, nx, ny, rng) if pat else ([None] * 4, [None] * 4))
+    kw = dict(limiters=lims, a_beta=1.1, bc_x=1, bc_y=1, precision=prec)
+    bs = BatchSolver(u0s, **kw)
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_set_boundary(bs.ctx, W, gpu.ones(70, dtype=gpu.uint8, device="cuda"))
+    assert e.value.status == B.LBM_ENOTSUP
+    for i, (kinds, states) in enumerate(descs):
+        for side in range(4):
+            if kinds[side] is not None:
+                bs.set_boundary(i, side, kinds[side], states[side])
+    bs.step(8)
+    bs.step_graph(4)
+    for i, u in enumerate(u0s):
+        ny, nx = u.shape[1:]
+        kinds, states = descs[i]
+        s = Solver(u, dx=1.0 / nx, **kw)
+        for side in range(4):
+            if kinds[side] is not None:
+                s.set_boundary(side, kinds[side], states[side])
+        s.step(12)
+        a = bs.moments(i).cpu().numpy()
+        b = s.moments().cpu().numpy()
+        assert np.array_equal(a, b), (i, np.abs(a - b).max())
+        assert bs.diagnostics(i)["lam"] == s.diagnostics()["lam"], i
+        s.close()
+        if prec == B.LBM_FP64 and i in (0, 2, 4):
+            cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, limiters=lims, a_beta=1.1, bc_x=1, bc_y=1,
+                                bnd_kind=tuple(kinds), bnd_state=tuple(states))
+            S, _ = oracle.init(cfg, u)
+            S, _, _, tot = oracle.run(cfg, S, 12)
+            assert np.array_equal(a, S[0:4]), i
+    bs.close()
