@@ -168,25 +168,45 @@ def draw_batch_case(i):
     c["grid"] = int(rng.choice([0, 0, 1, 2, 4]))
     c["mode"] = int(rng.integers(0, 2))
     c["seed"] = int(rng.integers(0, 1 << 30))
+    # per-instance boundary descriptions on outflow axes (half of the cases)
+    c["bnd"] = []
+    with_bnd = rng.random() < 0.5
+    for _ in c["sizes"]:
+        sides = [None] * 4
+        for side in range(4):
+            if with_bnd and (c["bc_x"] if side < 2 else c["bc_y"]) and rng.random() < 0.5:
+                sides[side] = str(rng.choice(["z", "w", "d", "m"]))
+        c["bnd"].append(sides)
     return c
 
 
 @pytest.mark.parametrize("i", range(N_BATCH_CASES))
 def test_batch_sweep_case(i, gpu):
-    """An uneven ensemble (one launch per step, then graph replays) against
+    """An uneven ensemble (one launch per step, then graph replays; in half
+    of the cases per-instance wall / Dirichlet / mixed boundary cells) against
     the oracle run of each instance alone (dx = 1/nx per instance): float64
     moments bit for bit, float32 state to 1e-5 relative L1 in density."""
     from paper_2411_15001_amd.solver import BatchSolver
 
     c = draw_batch_case(i)
     print("batch sweep case", i, c, flush=True)
-    u0s = []
+    u0s, descs = [], []
     for k, (nx, ny) in enumerate(c["sizes"]):
         u = cases.riemann4(max(nx, ny), rng=np.random.default_rng([c["seed"], k]))
         u0s.append(np.ascontiguousarray(u[:, :ny, :nx]))
+        # the boundary arrays of instance k, built as in the single-grid sweep
+        sub = dict(nx=nx, ny=ny, lims=c["lims"], order=c["order"], bc_x=c["bc_x"], bc_y=c["bc_y"],
+                   sponge=0, alpha=c["alpha"], beta=c["beta"], rlmp=(0.999, 1.001), fixed_a=False,
+                   bnd=c["bnd"][k], seed=c["seed"] + k)
+        _, _, kinds, states = build(sub)
+        descs.append((kinds, states))
     kw = dict(limiters=c["lims"], order=c["order"], alpha=c["alpha"], a_beta=c["beta"],
               bc_x=c["bc_x"], bc_y=c["bc_y"])
     bs = BatchSolver(u0s, precision=c["prec"], **kw)
+    for k, (kinds, states) in enumerate(descs):
+        for side in range(4):
+            if kinds[side] is not None:
+                bs.set_boundary(k, side, kinds[side], states[side])
     bs.set_launch(*c["launch"], groups_per_cu=c["grid"], strip_mode=c["mode"])
     bs.step(c["steps"])
     bs.step_graph(c["graph_steps"])
@@ -194,7 +214,8 @@ def test_batch_sweep_case(i, gpu):
     diags = [bs.diagnostics(k) for k in range(len(u0s))]  # before moments() clears the counters
     for k, u in enumerate(u0s):
         ny, nx = u.shape[1:]
-        cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, **kw)
+        kinds, states = descs[k]
+        cfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, bnd_kind=tuple(kinds), bnd_state=tuple(states), **kw)
         S, _ = oracle.init(cfg, u)
         S, _, _, tot = oracle.run(cfg, S, total)
         m = bs.moments(k, check=False)[0].cpu().numpy()
