@@ -17,11 +17,15 @@
  *
  * Parity unpinned (conventions the paper leaves open; the readings are fixed
  * here but no value printed in the paper or fixed by mathematics checks them):
- * the two zero-gradient ghost layers of outflow boundaries (bc_x / bc_y = 1;
- * only the convergence of Sod data to the exact Riemann solution checks them
- * indirectly), the sponge layer (sponge > 0), the event counters of orc_info
- * (n_guard, n_limited, n_bad), and evaluating M_k with the current a^n without
- * rescaling the distributions when a changes between steps.
+ * the event counters of orc_info (n_guard, n_limited, n_bad), and evaluating
+ * M_k with the current a^n without rescaling the distributions when a
+ * changes between steps.  The two zero-gradient ghost layers of outflow
+ * boundaries (a copy of the boundary cell's moment slot and all four
+ * distributions) and the sponge layer (theta = 0 on every face touching one
+ * of the first `sponge` cells of an outflow wall, ghosts included) are pinned
+ * by the tests against numpy restatements on explicitly padded fields
+ * (Example 3 with theta = 1, Lax-Friedrichs with theta = 0, the LMP factors
+ * of the boundary faces from two padded layers).
  *
  * Boundary cells of kind wall or Dirichlet (Section 4.8 states that it sets
  * boundary states "by setting the distribution to the corresponding
@@ -33,8 +37,10 @@
  * A ghost cell beyond a corner takes the x-side rule first (at the nearest
  * row), then the y-side rule.  lambda^n of a step also covers the Dirichlet
  * states (a^n must satisfy Bouchut's condition for every state the stencil
- * reads); the initial a^0 of orc_init covers u0 only.  Parity unpinned
- * except by the symmetry and uniform-flow checks of the tests.
+ * reads); the initial a^0 of orc_init covers u0 only.  Walls, corners
+ * included, are pinned by periodic runs of mirror-symmetric data (walls on
+ * two opposite sides, and on all four); the Dirichlet ghosts by the
+ * uniform-flow and zero-gradient-equivalence checks of the tests.
  */
 #ifndef VLBM_ORACLE_H
 #define VLBM_ORACLE_H

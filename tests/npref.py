@@ -115,3 +115,25 @@ def blended_fv(S, tx, ty, gamma, alpha, a):
     F = 0.5 * (east(f) + f) - k * (east(u) - u) + thx * dF
     G = 0.5 * (north(g) + g) - k * (north(u) - u) + thy * dG
     return u - (1.0 / a) * (F - west(F) + G - south(G))
+
+
+def theta_lmp(rs, D, kappa, muL, nuL, muR, nuR):
+    """Section 3.3.1, final case formula, blended as min(1, .) (Section 3.2):
+    1 if D = 0; kappa min(nu_R - rho*, rho* - mu_L) / D if D > 0;
+    -kappa min(rho* - mu_R, nu_L - rho*) / D if D < 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pos = kappa * np.minimum(nuR - rs, rs - muL) / D
+        neg = -kappa * np.minimum(rs - muR, nuL - rs) / D
+    t = np.where(D > 0, pos, np.where(D < 0, neg, 1.0))
+    return np.minimum(1.0, t)
+
+
+def pad(q, width, bc_x, bc_y):
+    """[..., ny, nx] field extended by `width` ghost cells on every side: a
+    periodic axis (bc 0) wraps, an outflow axis (bc 1) repeats the edge cell,
+    the zero-gradient condition of Section 4.2 applied to every plane."""
+    nd = q.ndim
+    wx = [(0, 0)] * (nd - 1) + [(width, width)]
+    wy = [(0, 0)] * (nd - 2) + [(width, width), (0, 0)]
+    q = np.pad(q, wx, mode="wrap" if bc_x == 0 else "edge")
+    return np.pad(q, wy, mode="wrap" if bc_y == 0 else "edge")
