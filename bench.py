@@ -59,8 +59,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid side (default 8192 for blast, 2048 for rarefaction)")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated forms (default fp32,fp64 for blast, fp64 for rarefaction)")
+    ap.add_argument("--bounds", default="lmp", choices=["lmp", "rlmp"],
+                    help="rarefaction workload: the density-bounds limiter")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
@@ -312,39 +316,62 @@ def _line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, roofli
 
 
 def bench_rarefaction(a):
-    """Near-vacuum double rarefaction 2048^2, FP64, PP + LMP + pressure,
-    outflow, a = 4 lambda (the LMP variant of the step)."""
+    """Near-vacuum double rarefaction (the bounds-limited variant of the
+    step): n x n (default 2048), outflow, a = 4 lambda, PP + LMP + pressure
+    (or PP + RLMP + pressure with --bounds rlmp); each form in --forms
+    (default fp64) is timed on its own context.  The first form heads the
+    line; every form's figures are under `forms`."""
     import torch
 
     from paper_2411_15001_amd import binding as B
     from paper_2411_15001_amd import cases
     from paper_2411_15001_amd.solver import Solver
 
-    n = 2048
-    s = Solver(cases.double_rarefaction(n, seed=0), limiters=B.LBM_RHO_PP | B.LBM_RHO_LMP | B.LBM_PRESSURE,
-               bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
-    if not a.no_autotune:
-        # tune on a developed flow (the limiters' slow paths are rare in the
-        # first steps), then restart from the initial state
-        init = s.get_state()
-        s.step(100)
-        s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
-        s.set_state(init)
-        s.moments(check=False)  # clears the event counters of the untimed steps
-        del init
-    s.step(a.warmup)
-    ms = _timed(lambda: s.step(a.steps), a.steps)
-    st = s.moments(check=False)[1]
-    avg = ms / a.steps
-    ach = 320.0 * n * n / (avg * 1e-3) / 1e9
-    _line(METRIC, n * n / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.warmup, avg, "f64",
-          {"workload": "near-vacuum double rarefaction 2048x2048, outflow, PP + LMP + pressure, "
-                       "a = 4 lambda, fp64 form", "grid": [n, n]},
-          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("rarefaction%d_fp64" % n, s.launch())},
-          status=int(st), launch=list(s.launch()),
-          **({} if a.no_cpu else {"cpu_baseline": cpu_rarefaction(n)}))
-    s.close()
+    n = a.n or 2048
+    forms_req = (a.forms or "fp64").split(",")
+    bound = B.LBM_RHO_RLMP if a.bounds == "rlmp" else B.LBM_RHO_LMP
+    lims = B.LBM_RHO_PP | bound | B.LBM_PRESSURE
+    u0t = torch.from_numpy(cases.double_rarefaction(n, seed=0)).cuda()
+    forms = {}
+    for form in forms_req:
+        prec = B.LBM_FP32_STATE if form == "fp32" else B.LBM_FP64
+        s = Solver(u0t, precision=prec, limiters=lims, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
+        if not a.no_autotune:
+            # tune on a developed flow (the limiters' slow paths are rare in
+            # the first steps), then restart from the initial state
+            init = s.get_state()
+            s.step(100)
+            s.autotune(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json"))
+            s.set_state(init)
+            s.moments(check=False)  # clears the event counters of the untimed steps
+            del init
+        s.step(a.warmup)
+        ms = _timed(lambda: s.step(a.steps), a.steps)
+        st = s.moments(check=False)[1]
+        d = s.diagnostics()
+        launch = list(s.launch())
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        avg = ms / a.steps
+        ach = BYTES_PER_CELL[form] * n * n / (avg * 1e-3) / 1e9
+        forms[form] = {
+            "value": n * n / (avg * 1e-3) / 1e9, "ms_per_step": avg, "status": int(st), "launch": launch,
+            "diag": {"lambda": d["lam"], "n_bad": d["n_bad"], "n_guard": d["n_guard"], "n_lmp": d["n_lmp"]},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": traffic_for("rarefaction%d_%s%s" % (n, "" if a.bounds == "lmp" else "rlmp_", form),
+                                                launch)}}
+        print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
+            form, forms[form]["value"], avg, 100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)
+    del u0t
+    H = forms[forms_req[0]]
+    _line(METRIC, H["value"], "GLUPS", a.steps, a.warmup, H["ms_per_step"],
+          "f32 (theta solve and CFL reduce f64)" if forms_req[0] == "fp32" else "f64",
+          {"workload": "near-vacuum double rarefaction %dx%d, outflow, PP + %s + pressure, "
+                       "a = 4 lambda, %s form" % (n, n, a.bounds.upper(), forms_req[0]), "grid": [n, n]},
+          H["roofline"], status=H["status"], launch=H["launch"], forms=forms,
+          **({} if a.no_cpu else {"cpu_baseline": cpu_rarefaction(min(n, 2048))}))
 
 
 def bench_batch(a):
@@ -472,6 +499,8 @@ def main():
     from paper_2411_15001_amd import cases
 
     torch.cuda.set_device(0)
+    a.n = a.n or 8192
+    a.forms = a.forms or "fp32,fp64"
     u0 = cases.blast(a.n, seed=0)
     u0t = torch.from_numpy(u0).cuda()
     del u0

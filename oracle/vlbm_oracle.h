@@ -27,9 +27,9 @@
  * (Example 3 with theta = 1, Lax-Friedrichs with theta = 0, the LMP factors
  * of the boundary faces from two padded layers).
  *
- * Boundary cells of kind wall or Dirichlet (Section 4.8 states that it sets
- * boundary states "by setting the distribution to the corresponding
- * Maxwellian" and uses a reflective symmetry wall, without further detail):
+ * Boundary cells of kind wall or Dirichlet (Section 4.8 imposes boundary
+ * states through the Maxwellians of those states and uses a reflective
+ * symmetry wall, without further detail):
  * ghost layer g beyond a wall holds the mirror image of interior cell g - 1
  * (normal momentum negated in the moment slot and in every distribution, the
  * two distributions moving along the wall normal exchanged); a Dirichlet
