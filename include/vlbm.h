@@ -55,7 +55,8 @@ typedef enum {
   LBM_ENOTSUP = 2,     /* valid but not supported by this entry point */
   LBM_EDEVICE = 3,     /* a HIP runtime call failed */
   LBM_EPOSITIVITY = 4, /* a cell with rho <= 0 or p <= 0 was produced */
-  LBM_ENONFINITE = 5,  /* reserved: non-finite values are reported as EPOSITIVITY */
+  LBM_ENONFINITE = 5,  /* a cell with a non-finite value (or wavespeed) was
+                          produced; takes precedence over LBM_EPOSITIVITY */
   LBM_EBOUCHUT = 6,    /* a < 2 lambda / (1 - alpha) in a fixed-a run (eq. (5)) */
   LBM_EGUARD = 7       /* a face intermediate state u* left the admissible set */
 } lbm_status;
@@ -93,8 +94,6 @@ typedef struct {
   int32_t precision;  /* LBM_FP64 or LBM_FP32_STATE */
   double eps;         /* epsilon of the PP and pressure limiters (1e-16) */
   double rlmp_lo, rlmp_hi; /* relaxed bound factors (0.999, 1.001) */
-  double theta_margin;/* LBM_FP32_STATE only: kappa is scaled by (1 - margin)
-                         in the limiters; must be 0 for LBM_FP64 */
   int32_t unsafe;     /* 1 allows alpha < 1/2 or beta < 1 (no positivity
                          guarantee); 0 rejects them */
 } lbm_params;
@@ -106,7 +105,7 @@ typedef struct {
   int64_t step;        /* steps taken since init */
   int64_t n_guard;     /* faces with u* outside the admissible set */
   int64_t n_limited;   /* faces with theta < 1 (left and bottom face of every cell) */
-  int64_t n_bad;       /* cells with rho <= 0, p <= 0 or a non-finite wavespeed */
+  int64_t n_bad;       /* non-admissible cells: n_nonfinite + n_rho + n_rhoe */
   int32_t bouchut;     /* a fixed a fell below 2 lambda / (1 - alpha) */
   int64_t n_lmp;       /* with LMP or RLMP limiting (order 2): cells whose new
                           density left the eq. (29) bounds [mu, nu] of the cell
@@ -114,6 +113,16 @@ typedef struct {
                           float64, 2e-6 with the float32 state).  Zero under LMP
                           (eq. (28)); RLMP relaxes the bounds, so it may count
                           there.  A check, not an error: no call fails on it. */
+  int64_t n_nonfinite; /* of n_bad: a component of (rho, m1, m2, E) or the
+                          wavespeed is not finite */
+  int64_t n_rho;       /* of n_bad: finite, rho <= 0 */
+  int64_t n_rhoe;      /* of n_bad: finite, rho > 0, internal energy
+                          rho e = E - |m|^2 / (2 rho) <= 0 (p <= 0) */
+  double min_rho;      /* minimum of rho over the finite cells of the current
+                          state of instance inst (+inf if none; NaN after
+                          lbm_step_between, whose state is in a caller buffer) */
+  double min_rhoe;     /* minimum of rho e over the same cells (Section 2: the
+                          scheme keeps rho > 0 and rho e > 0) */
 } lbm_diag;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -128,7 +137,8 @@ size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n,
  * u_k = M_k(u0; a^0), k = 1..4, with lambda^0 and a^0 from u0.
  * u0_dev: float64 [4][ny][nx] (rho, m1, m2, E), device memory, read only.
  * Synchronises once to check that every cell of u0 is admissible
- * (LBM_EPOSITIVITY otherwise; no context is returned).  On success *out owns a
+ * (LBM_ENONFINITE if a value is not finite, LBM_EPOSITIVITY if rho <= 0 or
+ * p <= 0; no context is returned then).  On success *out owns a
  * host context bound to `stream` (free with lbm_destroy). */
 lbm_status lbm_init(const lbm_params* p, const double* u0_dev, void* workspace_dev,
                     void* stream, lbm_ctx** out);
@@ -198,7 +208,9 @@ lbm_status lbm_moments(lbm_ctx* ctx, int32_t inst, double* u_out_dev);
  * host memory for 4 doubles.  Synchronises; clears no counter. */
 lbm_status lbm_totals(lbm_ctx* ctx, int32_t inst, double* totals_host);
 
-/* Diagnostics of instance `inst`; synchronises; does not clear counters. */
+/* Diagnostics of instance `inst`: the counters accumulated since the last
+ * lbm_moments, and the minima of rho and rho e of the current state (one
+ * reduction kernel).  Synchronises; does not clear counters. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t inst, lbm_diag* out);
 
 /* Copy the whole current state (layout above, lbm_state_bytes bytes) to /

@@ -59,7 +59,6 @@ class lbm_params(ctypes.Structure):
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
         ("sponge", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("eps", ctypes.c_double), ("rlmp_lo", ctypes.c_double), ("rlmp_hi", ctypes.c_double),
-        ("theta_margin", ctypes.c_double),
         ("unsafe", ctypes.c_int32),
     ]
 
@@ -70,6 +69,8 @@ class lbm_diag(ctypes.Structure):
         ("step", ctypes.c_int64), ("n_guard", ctypes.c_int64),
         ("n_limited", ctypes.c_int64), ("n_bad", ctypes.c_int64),
         ("bouchut", ctypes.c_int32), ("n_lmp", ctypes.c_int64),
+        ("n_nonfinite", ctypes.c_int64), ("n_rho", ctypes.c_int64), ("n_rhoe", ctypes.c_int64),
+        ("min_rho", ctypes.c_double), ("min_rhoe", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -152,12 +153,12 @@ def make_params(nx, ny, dx=None, gamma=1.4, alpha=0.5, order=2,
                 limiters=LBM_RHO_PP | LBM_PRESSURE, a_mode=LBM_A_DYNAMIC, a_beta=1.0,
                 a_fixed=0.0, bc_x=LBM_BC_PERIODIC, bc_y=LBM_BC_PERIODIC, sponge=0,
                 precision=LBM_FP64, eps=1e-16, rlmp_lo=0.999, rlmp_hi=1.001,
-                theta_margin=0.0, unsafe=0):
+                unsafe=0):
     if dx is None:
         dx = 1.0 / nx if nx > 0 else 1.0  # nx < 1 is refused by the library
     return lbm_params(nx, ny, dx, gamma, alpha, order, limiters,
                       a_mode, a_beta, a_fixed, bc_x, bc_y, sponge, precision, eps, rlmp_lo,
-                      rlmp_hi, theta_margin, unsafe)
+                      rlmp_hi, unsafe)
 
 
 def _ptr(t):

@@ -68,8 +68,6 @@ const char* check_params(const lbm_params* p) {
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_STATE) return "unknown precision";
   if (!(p->eps >= 0.0)) return "eps must be >= 0";
   if (!(p->rlmp_lo > 0.0 && p->rlmp_lo <= 1.0 && p->rlmp_hi >= 1.0)) return "bad RLMP factors";
-  if (!(p->theta_margin >= 0.0 && p->theta_margin < 1.0)) return "theta_margin must lie in [0, 1)";
-  if (p->precision == LBM_FP64 && p->theta_margin != 0.0) return "theta_margin is for LBM_FP32_STATE only";
   return nullptr;
 }
 
@@ -82,7 +80,6 @@ Scheme make_scheme(const lbm_params* p) {
   s.eps = p->eps;
   s.rlmp_lo = p->rlmp_lo;
   s.rlmp_hi = p->rlmp_hi;
-  s.theta_margin = p->theta_margin;
   s.a_mode = p->a_mode;
   s.order = p->order;
   s.limiters = (int)p->limiters;
@@ -129,6 +126,12 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
 }
 
 }  // namespace
+
+namespace vlbm {
+const char* host_check_params(const lbm_params* p) { return check_params(p); }
+Scheme host_make_scheme(const lbm_params* p) { return make_scheme(p); }
+void host_set_error(const char* m) { g_init_error = m; }
+}  // namespace vlbm
 
 struct lbm_ctx {
   lbm_params p;
@@ -427,11 +430,13 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   }
   for (int i = 0; i < n; ++i) {
     if (h[i].cnt[vlbm::CNT_BAD]) {
-      char buf[160];
-      snprintf(buf, sizeof(buf), "instance %d: %llu cells of u0 are not admissible (rho <= 0 or p <= 0)",
-               i, h[i].cnt[vlbm::CNT_BAD]);
+      const bool nf = h[i].cnt[vlbm::CNT_NONFINITE] != 0;
+      char buf[200];
+      snprintf(buf, sizeof(buf), "instance %d: %llu cells of u0 are not admissible (%llu non-finite, "
+               "%llu with rho <= 0, the others with p <= 0)", i, h[i].cnt[vlbm::CNT_BAD],
+               h[i].cnt[vlbm::CNT_NONFINITE], h[i].cnt[vlbm::CNT_RHO]);
       delete c;
-      return fail(nullptr, LBM_EPOSITIVITY, buf);
+      return fail(nullptr, nf ? LBM_ENONFINITE : LBM_EPOSITIVITY, buf);
     }
   }
   *out = c;
@@ -571,14 +576,19 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
   lbm_status st = read_slots(c, h);
   if (st != LBM_OK) return st;
   lbm_status res = LBM_OK;
-  unsigned long long bad = 0, guard = 0, bouchut = 0;
+  unsigned long long bad = 0, nonfinite = 0, guard = 0, bouchut = 0;
   for (int i = 0; i < c->n_inst; ++i) {
     bad += h[i].cnt[vlbm::CNT_BAD];
+    nonfinite += h[i].cnt[vlbm::CNT_NONFINITE];
     guard += h[i].cnt[vlbm::CNT_GUARD];
     bouchut |= h[i].cnt[vlbm::CNT_BOUCHUT];
   }
   char buf[160];
-  if (bad) {
+  if (nonfinite) {
+    snprintf(buf, sizeof(buf), "%llu cells with non-finite values were produced (%llu non-admissible in all)",
+             nonfinite, bad);
+    res = fail(c, LBM_ENONFINITE, buf);
+  } else if (bad) {
     snprintf(buf, sizeof(buf), "%llu non-admissible cells were produced", bad);
     res = fail(c, LBM_EPOSITIVITY, buf);
   } else if (guard) {
@@ -604,6 +614,21 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
 lbm_status lbm_diagnostics(lbm_ctx* c, int32_t inst, lbm_diag* d) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (inst < 0 || inst >= c->n_inst || !d) return fail(c, LBM_EINVAL, "bad instance or output");
+  // minima of rho and rho e of the current state (block partials in the
+  // workspace's reduction area, combined here); a detached context's state
+  // is in a caller buffer, so its minima are not available
+  const Inst& in = c->insts[inst];
+  const long long n = (long long)in.nx * in.ny;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, kTotalsBlocks);
+  std::vector<double> part;
+  if (!c->detached) {
+    double* dp = (double*)(c->ws + c->lay.red);
+    hipError_t e = vlbm::launch_minima(in, c->plane, c->cur(), dp, blocks, c->p.precision, c->stream);
+    part.resize((size_t)blocks * 2);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(part.data(), dp, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "minima");
+  }
   std::vector<Slots> h;
   lbm_status st = read_slots(c, h);
   if (st != LBM_OK) return st;
@@ -618,6 +643,20 @@ lbm_status lbm_diagnostics(lbm_ctx* c, int32_t inst, lbm_diag* d) {
   d->n_bad = s.cnt[vlbm::CNT_BAD];
   d->bouchut = (int32_t)s.cnt[vlbm::CNT_BOUCHUT];
   d->n_lmp = s.cnt[vlbm::CNT_LMP];
+  d->n_nonfinite = s.cnt[vlbm::CNT_NONFINITE];
+  d->n_rho = s.cnt[vlbm::CNT_RHO];
+  d->n_rhoe = s.cnt[vlbm::CNT_BAD] - s.cnt[vlbm::CNT_NONFINITE] - s.cnt[vlbm::CNT_RHO];
+  d->min_rho = NAN;
+  d->min_rhoe = NAN;
+  if (!part.empty()) {
+    double mr = INFINITY, me = INFINITY;
+    for (int b = 0; b < blocks; ++b) {
+      mr = std::min(mr, part[2 * (size_t)b]);
+      me = std::min(me, part[2 * (size_t)b + 1]);
+    }
+    d->min_rho = mr;
+    d->min_rhoe = me;
+  }
   return LBM_OK;
 }
 
@@ -831,10 +870,20 @@ lbm_status lbm_get_grid(const lbm_ctx* c, int32_t* groups_per_cu, int32_t* group
 lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (lbm_status st0 = require_attached(c)) return st0;
-  char key[160];
+  // cache key: everything that selects the kernel or shapes its work list —
+  // instance count, first instance, total cells, precision, limiters, order,
+  // boundary conditions, sponge, boundary descriptions, and a hash (FNV-1a)
+  // of every instance's sides, so that ensembles with the same first
+  // instance and cell count do not share an entry
+  uint32_t h = 2166136261u;
+  for (const Inst& in : c->insts)
+    for (int v : {in.nx, in.ny})
+      for (int b = 0; b < 4; ++b) h = (h ^ (uint32_t)((v >> (8 * b)) & 0xff)) * 16777619u;
+  char key[200];
   long long cells = c->plane;
-  snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d", c->n_inst, c->insts[0].nx,
-           c->insts[0].ny, cells, c->p.precision, c->p.limiters, c->p.order);
+  snprintf(key, sizeof(key), "n%d_nx%d_ny%d_cells%lld_p%d_lim%u_o%d_bc%d%d_s%d_b%d_h%08x", c->n_inst,
+           c->insts[0].nx, c->insts[0].ny, cells, c->p.precision, c->p.limiters, c->p.order, c->p.bc_x,
+           c->p.bc_y, c->p.sponge, c->has_bnd ? 1 : 0, h);
   // cache lookup: a flat JSON object {"key": [rows, waves, groups per CU,
   // strip mode], ...} (missing trailing values are 0)
   std::string text;

@@ -226,11 +226,16 @@ __device__ __forceinline__ void raise_lambda(unsigned long long* p, double lmax)
   if (v > seen) atomicMax(p, v);
 }
 
-// One lane per wave publishes the wave's wavespeed maximum and event counts.
+// One lane per wave publishes the wave's wavespeed maximum and event counts;
+// n_cls packs the non-finite count (bits 16 and up) and the rho <= 0 count
+// (low 16 bits) of the non-admissible cells.
 __device__ __forceinline__ void publish(Slots* sl, int slot, double lmax, unsigned n_bad,
-                                       unsigned n_guard, unsigned n_lim, unsigned n_lmp = 0) {
+                                       unsigned n_guard, unsigned n_lim, unsigned n_lmp,
+                                       unsigned n_nf, unsigned n_rho) {
   raise_lambda(&sl->lam[slot], lmax);
   if (n_bad) atomicAdd(&sl->cnt[CNT_BAD], (unsigned long long)n_bad);
+  if (n_nf) atomicAdd(&sl->cnt[CNT_NONFINITE], (unsigned long long)n_nf);
+  if (n_rho) atomicAdd(&sl->cnt[CNT_RHO], (unsigned long long)n_rho);
   if (n_guard) atomicAdd(&sl->cnt[CNT_GUARD], (unsigned long long)n_guard);
   if (n_lim) atomicAdd(&sl->cnt[CNT_LIMITED], (unsigned long long)n_lim);
   if (n_lmp) atomicAdd(&sl->cnt[CNT_LMP], (unsigned long long)n_lmp);
@@ -248,6 +253,33 @@ __device__ __forceinline__ double cell_wavespeed(double rho, double m1, double m
   const double l = sqrt(v1 * v1 + v2 * v2) + sqrt(gamma * p * ir);
   if (!(rho > 0.0) || !(p > 0.0) || !(l <= 1.79769313486231570e308)) return -1.0;
   return l;
+}
+
+// Class of a state that cell_wavespeed rejects, added to a lane's packed
+// count: 1 << 16 when a component, or else the wavespeed, is not finite; 1
+// when rho <= 0; 0 when rho > 0 and p <= 0 (p evaluated as in
+// cell_wavespeed).  Each lane counts at most 4096 rows of a strip, so the two
+// 16-bit fields do not overflow before the wave reduction unpacks them.
+__device__ __forceinline__ unsigned bad_class(double rho, double m1, double m2, double E,
+                                              double gamma) {
+  if (!isfinite(rho) || !isfinite(m1) || !isfinite(m2) || !isfinite(E)) return 1u << 16;
+  if (!(rho > 0.0)) return 1u;
+  const double ir = 1.0 / rho;
+  const double v1 = m1 * ir;
+  const double v2 = m2 * ir;
+  const double p = (gamma - 1.0) * (E - 0.5 * (m1 * v1 + m2 * v2));
+  return p > 0.0 ? (1u << 16) : 0u;
+}
+
+// Reduction over the wave of the packed class counts: (non-finite, rho <= 0).
+__device__ __forceinline__ void reduce_classes(unsigned cls, unsigned& n_nf, unsigned& n_rho) {
+  n_nf = cls >> 16;
+  n_rho = cls & 0xffffu;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    n_nf += __shfl_xor(n_nf, off, 64);
+    n_rho += __shfl_xor(n_rho, off, 64);
+  }
 }
 
 // Euler fluxes (Section 1) of one state.
@@ -283,7 +315,7 @@ __device__ __forceinline__ C maxw(int k, C u, C f, C g, C w, C r2a) {
 
 template <class T, class C>
 struct StepConst {
-  double a, kappa, klim, lam;
+  double a, kappa, lam;
   C w, r2a, r2k, ac, alpha, gm1;
 };
 
@@ -293,7 +325,6 @@ __device__ __forceinline__ StepConst<T, C> step_const(const Scheme& s, double la
   k.lam = lam;
   k.a = (s.a_mode == 1) ? s.a_fixed : 2.0 * s.beta * lam / (1.0 - s.alpha);
   k.kappa = 0.5 * k.a * (1.0 - s.alpha);
-  k.klim = k.kappa * (1.0 - s.theta_margin);
   k.w = (C)(0.25 * (1.0 - s.alpha));
   k.r2a = (C)(1.0 / (2.0 * k.a));
   k.r2k = (C)(1.0 / (2.0 * k.kappa));
@@ -428,7 +459,7 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
   C pu[4] = {}, pg[4] = {}, pM3[4] = {}, pd3[4] = {}, pP[4] = {};
 
   double lmax = 0.0;
-  unsigned n_bad = 0, n_guard = 0, n_lim = 0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_cls = 0;
 
   T raw[20], hraw[8];
   // with boundary descriptions, ghost rows, columns past the edge and the
@@ -536,9 +567,9 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     }
     int gx, gy, gw;
     const C zero = C(0);
-    double thx = face_theta<LIMS>(sc, usx, dF, K.klim, zero, zero, zero, zero, gx);
-    double thy = face_theta<LIMS>(sc, usy, dG, K.klim, zero, zero, zero, zero, gy);
-    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.klim, zero, zero, zero, zero, gw);
+    double thx = face_theta<LIMS>(sc, usx, dF, K.kappa, zero, zero, zero, zero, gx);
+    double thy = face_theta<LIMS>(sc, usy, dG, K.kappa, zero, zero, zero, zero, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, zero, zero, zero, zero, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
@@ -617,10 +648,13 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     if (row1 && lane_out) {
       const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
                                       (double)(T)fin[3], sc.gamma);
-      if (l < 0.0)
+      if (l < 0.0) {
         n_bad += 1;
-      else
+        n_cls += bad_class((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2], (double)(T)fin[3],
+                           sc.gamma);
+      } else {
         lmax = vmax(lmax, l);
+      }
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -638,7 +672,9 @@ __device__ __forceinline__ void march_short(const StepArgs& A, const Inst& in, S
     n_guard += __shfl_xor(n_guard, off, 64);
     n_lim += __shfl_xor(n_lim, off, 64);
   }
-  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim);
+  unsigned n_nf, n_rho;
+  reduce_classes(n_cls, n_nf, n_rho);
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, 0, n_nf, n_rho);
 }
 
 // One aligned strip of the bounds-limited scheme (LMP / RLMP, eq. (29)):
@@ -694,7 +730,7 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   C opr = C(0), opm = C(0), hpy = C(0);
 
   double lmax = 0.0;
-  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_lmp = 0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_lmp = 0, n_cls = 0;
   // float64 state: the stores of a row are issued at the top of the next
   // iteration, right after its prefetch, so that they complete under that
   // iteration's compute rather than ahead of its wait for the prefetched
@@ -874,9 +910,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
     const C muE = from_right_or(mu1, hmu);
     const C nuE = from_right_or(nu1, hnu);
     int gx, gy, gw;
-    double thx = face_theta<LIMS>(sc, pusx, pdF, K.klim, mu1, nu1, muE, nuE, gx);
-    double thy = face_theta<LIMS>(sc, pusy, pdG, K.klim, pmu, pnu, mu1, nu1, gy);
-    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.klim, hmu, hnu, mu1, nu1, gw);
+    double thx = face_theta<LIMS>(sc, pusx, pdF, K.kappa, mu1, nu1, muE, nuE, gx);
+    double thy = face_theta<LIMS>(sc, pusy, pdG, K.kappa, pmu, pnu, mu1, nu1, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, hmu, hnu, mu1, nu1, gw);
     if (sponge) {
       if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi + 1, L - 1, nx, ny)) thx = 0.0;
       if (in_sponge(sc, gi, L - 2, nx, ny) || in_sponge(sc, gi, L - 1, nx, ny)) thy = 0.0;
@@ -964,10 +1000,13 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
       // wavespeed of the stored new state, in float64
       const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
                                       (double)(T)fin[3], sc.gamma);
-      if (l < 0.0)
+      if (l < 0.0) {
         n_bad += 1;
-      else
+        n_cls += bad_class((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2], (double)(T)fin[3],
+                           sc.gamma);
+      } else {
         lmax = vmax(lmax, l);
+      }
       // LMP check: the stored density against the eq. (29) bounds of the
       // cell (pmu, pnu: row L - 2), beyond the rounding of the update
       const double r = (double)(T)fin[0], lo = (double)pmu, hi = (double)pnu;
@@ -1006,7 +1045,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
     n_guard += __shfl_xor(n_guard, off, 64);
     n_lim += __shfl_xor(n_lim, off, 64);
   }
-  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp);
+  unsigned n_nf, n_rho;
+  reduce_classes(n_cls, n_nf, n_rho);
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp, n_nf, n_rho);
 }
 
 // The step kernel: T the state's storage type, C its arithmetic type, LMP the
@@ -1058,37 +1099,49 @@ __global__ __launch_bounds__(256) void lambda_kernel(const Src* __restrict__ u, 
                                                      long long n, double gamma, Slots* sl,
                                                      int slot) {
   double lmax = 0.0;
-  unsigned bad = 0;
+  unsigned bad = 0, nf = 0, nr = 0;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
     const double r = (double)(T)u[c], m1 = (double)(T)u[plane + c],
                  m2 = (double)(T)u[2 * plane + c], E = (double)(T)u[3 * plane + c];
     const double l = cell_wavespeed(r, m1, m2, E, gamma);
-    if (l < 0.0)
+    if (l < 0.0) {
       bad += 1;
-    else
+      const unsigned k = bad_class(r, m1, m2, E, gamma);
+      nf += k >> 16;
+      nr += k & 0xffffu;
+    } else {
       lmax = vmax(lmax, l);
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
     bad += __shfl_xor(bad, off, 64);
+    nf += __shfl_xor(nf, off, 64);
+    nr += __shfl_xor(nr, off, 64);
   }
   // block reduction (every thread of the block reaches the barrier), then one
   // update per block
   __shared__ double wl[4];
-  __shared__ unsigned wb[4];
+  __shared__ unsigned wb[4][3];
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     wl[w] = lmax;
-    wb[w] = bad;
+    wb[w][0] = bad;
+    wb[w][1] = nf;
+    wb[w][2] = nr;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     lmax = vmax(vmax(wl[0], wl[1]), vmax(wl[2], wl[3]));
-    bad = wb[0] + wb[1] + wb[2] + wb[3];
+    bad = wb[0][0] + wb[1][0] + wb[2][0] + wb[3][0];
+    nf = wb[0][1] + wb[1][1] + wb[2][1] + wb[3][1];
+    nr = wb[0][2] + wb[1][2] + wb[2][2] + wb[3][2];
     raise_lambda(&sl->lam[slot], lmax);
     if (bad) atomicAdd(&sl->cnt[CNT_BAD], (unsigned long long)bad);
+    if (nf) atomicAdd(&sl->cnt[CNT_NONFINITE], (unsigned long long)nf);
+    if (nr) atomicAdd(&sl->cnt[CNT_RHO], (unsigned long long)nr);
   }
 }
 
@@ -1143,6 +1196,40 @@ __global__ __launch_bounds__(256) void totals_kernel(const T* __restrict__ S, lo
     for (int q = 1; q < 4; ++q) dd_add(h, l, wsum[q][k][0], wsum[q][k][1]);
     part[((long long)blockIdx.x * 4 + k) * 2] = h;
     part[((long long)blockIdx.x * 4 + k) * 2 + 1] = l;
+  }
+}
+
+// Minima of rho and of the internal energy density rho e = E - |m|^2 / (2 rho)
+// over the cells of the moment slot whose four components are finite, one
+// partial pair per block (+inf where a block has no such cell).
+template <class T>
+__global__ __launch_bounds__(256) void minima_kernel(const T* __restrict__ S, long long plane,
+                                                     long long n, double* __restrict__ part) {
+  double mr = kHuge, me = kHuge;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double r = (double)S[c], m1 = (double)S[plane + c], m2 = (double)S[2 * plane + c],
+                 E = (double)S[3 * plane + c];
+    if (!isfinite(r) || !isfinite(m1) || !isfinite(m2) || !isfinite(E)) continue;
+    mr = vmin(mr, r);
+    me = vmin(me, E - 0.5 * (m1 * m1 + m2 * m2) / r);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mr = vmin(mr, __shfl_xor(mr, off, 64));
+    me = vmin(me, __shfl_xor(me, off, 64));
+  }
+  // every thread of the block reaches the barrier
+  __shared__ double wm[4][2];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    wm[w][0] = mr;
+    wm[w][1] = me;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * (long long)blockIdx.x] = vmin(vmin(wm[0][0], wm[1][0]), vmin(wm[2][0], wm[3][0]));
+    part[2 * (long long)blockIdx.x + 1] = vmin(vmin(wm[0][1], wm[1][1]), vmin(wm[2][1], wm[3][1]));
   }
 }
 
@@ -1346,6 +1433,18 @@ hipError_t launch_totals(const Inst& in, long long plane, const void* S, double*
                        (const double*)S + in.off, plane, n, part);
   else
     hipLaunchKernelGGL((totals_kernel<float>), dim3(blocks), dim3(256), 0, s,
+                       (const float*)S + in.off, plane, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_minima(const Inst& in, long long plane, const void* S, double* part,
+                         int blocks, int precision, hipStream_t s) {
+  const long long n = (long long)in.nx * in.ny;
+  if (precision == 0)
+    hipLaunchKernelGGL((minima_kernel<double>), dim3(blocks), dim3(256), 0, s,
+                       (const double*)S + in.off, plane, n, part);
+  else
+    hipLaunchKernelGGL((minima_kernel<float>), dim3(blocks), dim3(256), 0, s,
                        (const float*)S + in.off, plane, n, part);
   return hipGetLastError();
 }

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vlbm.h"
+
 namespace vlbm {
 
 // Scheme parameters shared by every instance of a context.
 struct Scheme {
-  double gamma, alpha, beta, a_fixed, eps, rlmp_lo, rlmp_hi, theta_margin;
+  double gamma, alpha, beta, a_fixed, eps, rlmp_lo, rlmp_hi;
   int a_mode, order, limiters, bc_x, bc_y, sponge;
 };
 
@@ -36,9 +38,20 @@ struct BndDesc {
 struct alignas(128) Slots {
   unsigned long long lam[3]; // bit patterns of non-negative doubles
   double t[3];
-  unsigned long long cnt[5]; // guard, limited, bad, bouchut, lmp (cumulative)
+  // guard, limited, bad, bouchut, lmp, non-finite, rho <= 0 (cumulative); of
+  // the bad cells, those neither non-finite nor with rho <= 0 have p <= 0
+  unsigned long long cnt[7];
 };
-enum { CNT_GUARD = 0, CNT_LIMITED = 1, CNT_BAD = 2, CNT_BOUCHUT = 3, CNT_LMP = 4, CNT_N = 5 };
+enum {
+  CNT_GUARD = 0,
+  CNT_LIMITED = 1,
+  CNT_BAD = 2,
+  CNT_BOUCHUT = 3,
+  CNT_LMP = 4,
+  CNT_NONFINITE = 5,
+  CNT_RHO = 6,
+  CNT_N = 7
+};
 static_assert(sizeof(Slots) == 128, "one 128-byte record per instance");
 
 struct StepArgs {
@@ -79,6 +92,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_i
                                int slot, int precision, hipStream_t s);
 hipError_t launch_moments(const Inst& in, long long plane, const void* S,
                           double* out, int precision, hipStream_t s);
+// Block minima of rho and of rho e = E - |m|^2 / (2 rho) over the finite
+// cells of the moment slot, part[blocks][2].
+hipError_t launch_minima(const Inst& in, long long plane, const void* S, double* part,
+                         int blocks, int precision, hipStream_t s);
 // Double-double partial totals of the moment slot, part[blocks][4][2]; the
 // grid is `blocks` workgroups of 256 threads.
 hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
@@ -101,5 +118,11 @@ hipError_t launch_adjoint_step(const Scheme& sc, const Inst& in, long long plane
 hipError_t launch_adjoint_init(const Scheme& sc, const Inst& in, const double* u0,
                                const double* Ubar0, double* u0bar,
                                const Slots* slots, int slot, hipStream_t s);
+
+// Host helpers of the C ABI (api.hip): parameter checks (NULL when valid),
+// the kernels' scheme record, and the message lbm_last_error(NULL) returns.
+const char* host_check_params(const lbm_params* p);
+Scheme host_make_scheme(const lbm_params* p);
+void host_set_error(const char* m);
 
 }  // namespace vlbm

@@ -29,7 +29,7 @@ def test_host_side_validation():
     p = B.make_params(64, 64)
     assert B.lbm_workspace_bytes(p) > 20 * 64 * 64 * 8 * 2
     for bad in (dict(alpha=0.3), dict(gamma=1.0), dict(order=3), dict(a_beta=0.5),
-                dict(limiters=16), dict(precision=2), dict(theta_margin=0.1),
+                dict(limiters=16), dict(precision=2),
                 dict(a_mode=1, a_fixed=0.0)):
         assert B.lbm_workspace_bytes(B.make_params(64, 64, **bad)) == 0, bad
     assert B.lbm_workspace_bytes(B.make_params(64, 64, alpha=0.3, unsafe=1)) > 0

@@ -97,7 +97,15 @@ def test_batch_autotune_and_cache(tmp_path):
     # a second context reads the cached entry
     again = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
     assert again.autotune(cache) == (rows, waves, grid, mode)
-    for x in (bs, ref, again):
+    # an ensemble with the same first instance and cell count but other
+    # sides, and one with other boundary conditions, get entries of their own
+    other = batch([u0s[0], u0s[3], u0s[2], u0s[1]], precision=B.LBM_FP32_STATE, a_beta=1.1, bc_x=1, bc_y=1)
+    other.autotune(cache)
+    assert open(cache).read().count("[") == 2
+    per = batch(u0s, precision=B.LBM_FP32_STATE, a_beta=1.1)
+    per.autotune(cache)
+    assert open(cache).read().count("[") == 3
+    for x in (bs, ref, again, other, per):
         x.close()
 
 
