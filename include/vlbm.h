@@ -331,6 +331,34 @@ lbm_status lbm_set_instance_boundary(lbm_ctx* ctx, int32_t inst, int32_t side,
 lbm_status lbm_set_grid(lbm_ctx* ctx, int32_t groups_per_cu);
 lbm_status lbm_get_grid(const lbm_ctx* ctx, int32_t* groups_per_cu, int32_t* groups);
 
+/* For callers that cannot allocate memory (code under hipGraph capture, tight
+ * serving loops, harnesses that forbid allocation): one time step of a single
+ * instance without a context or workspace.  src_dev holds the state (layout
+ * above, 20 planes of nx * ny cells of the params' precision) and dst_dev
+ * receives the next one; both are caller device buffers that must not
+ * overlap.  Every parameter of lbm_params applies as in lbm_init (periodic and
+ * outflow boundaries, sponge layers; no wall or Dirichlet cells).  lambda^n
+ * is reduced from src_dev itself, so the call does not depend on a previous
+ * one; the step is the one lbm_step_between computes for the same state
+ * (bit for bit), with the time counted from 0 (diag_host->t = dt).
+ * The call allocates nothing: the per-step scalars (lambda slots, time,
+ * event counters) live in a static device array of LBM_NOALLOC_SCRATCH_BYTES
+ * bytes that the library holds on each device it runs on until the process
+ * ends (one 128-byte record is used).  It does not grow with the grid: any
+ * single-instance grid the library accepts (nx, ny < 2^30, nx * ny < 2^32;
+ * LBM_EINVAL beyond) runs with it.  Every call on a device shares that
+ * device's array and clears it first, so calls that overlap on one device
+ * (concurrent streams or threads) race and their results are unspecified.
+ * Enqueued on `stream` (hipStream_t as void*; NULL = default stream).  With
+ * diag_host == NULL the call is asynchronous and graph-capturable (fills,
+ * reductions and the step are kernels); with a host lbm_diag it synchronises
+ * the stream, fills lambda (lambda^n), a (a^n), t (dt^n), step (1) and the
+ * counters of the new state (min_rho, min_rhoe: NaN), and returns the
+ * step's first event as lbm_moments does. */
+#define LBM_NOALLOC_SCRATCH_BYTES 256
+lbm_status lbm_step_noalloc(const lbm_params* p, const void* src_dev, void* dst_dev, void* stream,
+                            lbm_diag* diag_host);
+
 const char* lbm_status_string(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* ctx);
 void lbm_destroy(lbm_ctx* ctx);

@@ -44,7 +44,7 @@ EXPORTS = [
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_step_between", "lbm_step_adjoint",
     "lbm_step_adjoint_theta", "lbm_init_adjoint", "lbm_autotune", "lbm_set_launch", "lbm_get_launch",
     "lbm_set_grid", "lbm_get_grid", "lbm_set_strip_mode", "lbm_get_strip_mode", "lbm_set_boundary",
-    "lbm_set_instance_boundary",
+    "lbm_set_instance_boundary", "lbm_step_noalloc",
     "lbm_status_string", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -121,6 +121,7 @@ def lib():
         L.lbm_set_boundary.argtypes = [vp, i32, vp, vp]
         L.lbm_set_instance_boundary.argtypes = [vp, i32, i32, vp, vp]
         L.lbm_get_strip_mode.argtypes = [vp, i32p]
+        L.lbm_step_noalloc.argtypes = [pp, vp, vp, vp, ctypes.POINTER(lbm_diag)]
         L.lbm_get_grid.argtypes = [vp, i32p, i32p]
         L.lbm_status_string.argtypes = [ctypes.c_int]
         L.lbm_status_string.restype = ctypes.c_char_p
@@ -281,6 +282,25 @@ def lbm_step_between(ctx, src, dst, theta_x=None, theta_y=None):
         _require_cuda(theta_y, torch.float64, (ny + 1) * nx, "theta_y")
         tx, ty = _ptr(theta_x), _ptr(theta_y)
     return _check(lib().lbm_step_between(ctx, _ptr(src), _ptr(dst), tx, ty), ctx)
+
+
+def lbm_step_noalloc(params, src, dst, diag=True, check=True):
+    """One step of a single instance from the state in src to dst (device
+    tensors of 20 * nx * ny elements of the params' precision) without a
+    context; returns (status, lbm_diag or None).  With diag=False the call is
+    asynchronous on torch's current stream."""
+    import torch
+
+    dt = torch.float64 if params.precision == LBM_FP64 else torch.float32
+    n = 20 * params.nx * params.ny
+    _require_cuda(src, dt, n, "src")
+    _require_cuda(dst, dt, n, "dst")
+    d = lbm_diag() if diag else None
+    st = lib().lbm_step_noalloc(ctypes.byref(params), _ptr(src), _ptr(dst), _stream(),
+                                ctypes.byref(d) if diag else None)
+    if check:
+        _check(st, None)
+    return st, d
 
 
 def lbm_moments(ctx, inst, out, check=True):

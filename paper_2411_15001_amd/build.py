@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libvlbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("step.hip", "adjoint.hip", "api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("step.hip", "adjoint.hip", "api.hip", "noalloc.hip")]
 HEADERS = [os.path.join(CSRC, "vlbm_internal.h"), os.path.join(ROOT, "include", "vlbm.h")]
 
 HIPCC_FLAGS = [
