@@ -36,6 +36,8 @@ RHO_RLMP = 4
 PRESSURE = 8
 A_DYNAMIC = 0
 A_FIXED = 1
+BLEND_FACE = 0
+BLEND_CELL = 1
 PERIODIC = 0
 OUTFLOW = 1
 
@@ -70,6 +72,7 @@ class Params(ctypes.Structure):
         ("rlmp_hi", ctypes.c_double),
         ("bnd_kind", ctypes.POINTER(ctypes.c_uint8) * 4),
         ("bnd_state", ctypes.POINTER(ctypes.c_double) * 4),
+        ("blend", ctypes.c_int32),
     ]
 
 
@@ -148,6 +151,9 @@ class Config:
     # and Dirichlet moments, float64 [4, len] or None
     bnd_kind: tuple = (None, None, None, None)
     bnd_state: tuple = (None, None, None, None)
+    # BLEND_FACE (Section 3.2) or BLEND_CELL (the per-cell blending of
+    # Section 3.1, an ablation)
+    blend: int = 0
 
     def params(self) -> Params:
         dx = self.dx if self.dx is not None else 1.0 / self.nx
@@ -166,6 +172,7 @@ class Config:
                 st = np.ascontiguousarray(st, dtype=np.float64)
                 keep.append(st)
                 P.bnd_state[side] = st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        P.blend = self.blend
         P._keep = keep  # the arrays outlive the call that receives P
         return P
 

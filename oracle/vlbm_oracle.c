@@ -180,6 +180,7 @@ static int check_params(const orc_params* P) {
   if (P->bc_x < 0 || P->bc_x > 1 || P->bc_y < 0 || P->bc_y > 1) return -1;
   if (P->a_mode == ORC_A_FIXED && !(P->a_fixed > 0.0)) return -1;
   if (P->a_mode == ORC_A_DYNAMIC && !(P->a_beta > 0.0)) return -1;
+  if (P->blend != ORC_BLEND_FACE && P->blend != ORC_BLEND_CELL) return -1;
   for (int side = 0; side < 4; ++side) {
     const uint8_t* k = P->bnd_kind[side];
     if (!k) continue;
@@ -278,6 +279,36 @@ static double face_theta(const orc_params* P, const face_t* fc, double kappa,
                                   P->rlmp_lo * muR, P->rlmp_hi * nuR));
   if (P->limiters & ORC_PRESSURE) t = dmin(t, orc_theta_p(fc->us, fc->dF, kappa, P->eps));
   return t;
+}
+
+/* Per-cell blending (Section 3.1, eq. (naive_blending)): the distribution
+ * k leaving the upwind cell U = (i - alpha_k, j - beta_k) is
+ * M_k(u_U) + theta_U d_k(U), and the rest population of the cell itself is
+ * M_5 + theta_ij (M_5 - u_5) with u_5 = u - sum_k u_k (eq. (27)), so the
+ * moment slot becomes
+ *   u^{n+1} = alpha u + sum over the four faces of (incoming distribution
+ *             - theta_ij times the own distribution leaving through it),
+ * grouped by face in the order W, E, S, N as in the face-blended update.
+ * thW .. thN are the factors of the four upwind cells, thC the cell's own. */
+static void update_cell_percell(const cell_t_d* C, const cell_t_d* W, const cell_t_d* E,
+                                const cell_t_d* Sth, const cell_t_d* N, double thC, double thW,
+                                double thE, double thS, double thN, double alpha, double out[20]) {
+  for (int c = 0; c < 4; ++c) {
+    const double u1n = W->M[0][c] + thW * W->d[0][c];
+    const double u2n = E->M[1][c] + thE * E->d[1][c];
+    const double u3n = Sth->M[2][c] + thS * Sth->d[2][c];
+    const double u4n = N->M[3][c] + thN * N->d[3][c];
+    double un = alpha * C->u[c];
+    un = un + (u1n - thC * C->d[1][c]);
+    un = un + (u2n - thC * C->d[0][c]);
+    un = un + (u3n - thC * C->d[3][c]);
+    un = un + (u4n - thC * C->d[2][c]);
+    out[c] = un;
+    out[4 + c] = u1n;
+    out[8 + c] = u2n;
+    out[12 + c] = u3n;
+    out[16 + c] = u4n;
+  }
 }
 
 int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x,
@@ -381,7 +412,40 @@ int orc_step(const orc_params* P, const double* S, double* Snew, double* theta_x
   }
 
   /* S7: collide and stream. */
-  update_grid_d(P, T, gw, tx, ty, Snew);
+  if (P->blend == ORC_BLEND_CELL) {
+    /* theta_ij = min of the cell's four face factors, for the interior
+     * cells; a ghost cell takes the factor of the cell it copies (periodic
+     * wrap or the nearest cell), read through map_index */
+    double* tc = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+    if (!tc) return -2;
+    n_limited = 0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double t = tx[(size_t)j * (nx + 1) + i];
+        t = dmin(t, tx[(size_t)j * (nx + 1) + i + 1]);
+        t = dmin(t, ty[(size_t)j * nx + i]);
+        t = dmin(t, ty[(size_t)(j + 1) * nx + i]);
+        tc[(size_t)j * nx + i] = t;
+        n_limited += (t < 1.0);
+      }
+    const size_t plane = (size_t)nx * (size_t)ny;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+      for (int i = 0; i < nx; ++i) {
+        const size_t pc = (size_t)(j + gw) * pw + (size_t)(i + gw);
+        const int iw = map_index(i - 1, nx, P->bc_x), ie = map_index(i + 1, nx, P->bc_x);
+        const int js = map_index(j - 1, ny, P->bc_y), jn = map_index(j + 1, ny, P->bc_y);
+        double out[20];
+        update_cell_percell(&T[pc], &T[pc - 1], &T[pc + 1], &T[pc - pw], &T[pc + pw],
+                            tc[(size_t)j * nx + i], tc[(size_t)j * nx + iw], tc[(size_t)j * nx + ie],
+                            tc[(size_t)js * nx + i], tc[(size_t)jn * nx + i], P->alpha, out);
+        for (int q = 0; q < 20; ++q) Snew[(size_t)q * plane + (size_t)j * nx + i] = out[q];
+      }
+    }
+    free(tc);
+  } else {
+    update_grid_d(P, T, gw, tx, ty, Snew);
+  }
 
   /* LMP check: the new density of every cell against its eq. (29) bounds. */
   int64_t n_lmp = 0;

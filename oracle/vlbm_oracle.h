@@ -90,14 +90,27 @@ typedef struct {
    * two cells along their axis. */
   const uint8_t* bnd_kind[4];
   const double* bnd_state[4];
+  /* ORC_BLEND_FACE: the face blending of Section 3.2 (eqs. (25), (27)), the
+   * method.  ORC_BLEND_CELL: the per-cell blending that Section 3.1 states
+   * first and sets aside (eq. (naive_blending)): every distribution leaving
+   * a cell is blended with that cell's factor theta_ij.  The paper leaves
+   * theta_ij open; the reading here is the smallest of the factors of the
+   * cell's four faces (computed as for ORC_BLEND_FACE), and a ghost cell
+   * takes the factor of the cell its state is copied from.  An ablation:
+   * it conserves the moments but has no positivity guarantee. */
+  int32_t blend;
 } orc_params;
+
+#define ORC_BLEND_FACE 0
+#define ORC_BLEND_CELL 1
 
 typedef struct {
   double lambda;     /* lambda^n of the input state */
   double a, dt, kappa;
   double lambda_new; /* lambda^{n+1} of the output state */
   int64_t n_guard;   /* faces whose intermediate state left the admissible set */
-  int64_t n_limited; /* faces with theta < 1 (left and bottom faces of every cell) */
+  int64_t n_limited; /* faces with theta < 1 (left and bottom faces of every
+                        cell); with ORC_BLEND_CELL, cells with theta_ij < 1 */
   int64_t n_bad;     /* output cells with rho <= 0, p <= 0 or non-finite wavespeed */
   int32_t bouchut;   /* 1 if a < 2 lambda / (1 - alpha) */
   int64_t n_lmp;     /* with LMP or RLMP limiting: output cells whose new density
