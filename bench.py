@@ -67,13 +67,21 @@ def parse():
                     help="rarefaction workload: the density-bounds limiter")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=80)
+    ap.add_argument("--cpu-n", type=int, default=8192)
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="oracle steps of the multi-threaded CPU sample (the single-threaded one takes 1)")
+    ap.add_argument("--error-steps", type=int, default=500,
+                    help="blast: steps after which the FP32 form's density is compared (the workload's 500)")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="blast: skip the FP32 form's error against the oracle at 1024^2")
     ap.add_argument("--workload", default="blast", choices=["blast", "rarefaction", "batch", "adjoint"],
                     help="blast: the headline 8192^2 line; the others time the LMP, batching and "
                          "differentiation forms on their own workloads")
     ap.add_argument("--no-per-class", action="store_true",
                     help="batch workload: skip the per-size-class timings")
+    ap.add_argument("--record-traffic", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV LINE_JSON [TRACE_STATS_CSV]: record the counters of a "
+                         "profiled run of this script into profiles/traffic_step.json and exit")
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -93,7 +101,7 @@ def calibration_copy(gib):
     return {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
 
 
-def time_form(form, u0t, n, steps, warmup, autotune):
+def time_form(form, u0t, n, steps, warmup, autotune, total_steps=0):
     import torch
 
     from paper_2411_15001_amd import binding as B
@@ -120,6 +128,9 @@ def time_form(form, u0t, n, steps, warmup, autotune):
     ms = e0.elapsed_time(e1)
     tot1 = s.totals()
     drift = max(abs(b - a) for a, b in zip(tot0, tot1)) / (abs(tot0[0]) + abs(tot0[3]))
+    # untimed: on to the workload's full step count for the error comparison
+    if total_steps > warmup + steps:
+        s.step(total_steps - warmup - steps)
     m, st = s.moments(check=False)
     rho = m[0].clone()
     del m
@@ -214,7 +225,9 @@ def traffic_for(key, launch):
     return entry.get("bytes_per_launch")
 
 
-def cpu_baseline(n, steps):
+def _oracle_blast_rate(n, steps):
+    """FP64 oracle on the blast workload, n x n, `steps` steps; returns
+    (GLUPS, seconds, threads)."""
     import oracle
     from paper_2411_15001_amd import cases
 
@@ -222,13 +235,152 @@ def cpu_baseline(n, steps):
     u0 = cases.blast(n, seed=0)
     cfg = oracle.Config(nx=n, ny=n, limiters=oracle.RHO_PP | oracle.PRESSURE)
     S, _ = oracle.init(cfg, u0)
+    del u0
     t0 = time.perf_counter()
     oracle.run(cfg, S, steps)
     dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": "FP64 oracle on the blast workload at %dx%d for %d steps (%.1f s), "
-                      "OpenMP over rows" % (n, n, steps, dt)}
+    return n * n * steps / dt / 1e9, dt, oracle.num_threads()
+
+
+def _counter_rows(csv_path, counter):
+    """(kernel name, value) of every dispatch of one counter in a rocprofv3
+    counter-collection CSV."""
+    import csv
+
+    out = []
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def record_traffic(fetch_csv, write_csv, line_path, trace_csv=None):
+    """Record the measured HBM bytes per launch of the step kernels of one
+    benchmark run into profiles/traffic_step.json.  fetch_csv / write_csv:
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) of the same
+    bench.py command, whose JSON line is in line_path; run with --calib-gib,
+    they also hold the plain copy kernel whose counters give the bytes per
+    KiB read (the copy moves known bytes).  Each form's step kernel is told
+    apart by its storage type (double / float).  trace_csv: optional
+    rocprofv3 --stats kernel summary of the same command, for the average
+    launch time."""
+    import csv
+
+    line = json.loads(open(line_path).read().strip().splitlines()[-1])
+    fetch = _counter_rows(fetch_csv, "FETCH_SIZE")
+    write = _counter_rows(write_csv, "WRITE_SIZE")
+    calib = line.get("calibration_copy")
+    try:
+        with open(PMC_FILE) as f:
+            rec = json.load(f)
+    except OSError:
+        rec = {}
+    if calib:
+        cf = [v for k, v in fetch if "copyBuffer" in k]
+        cw = [v for k, v in write if "copyBuffer" in k]
+        copy_kib = calib["bytes_read"] / calib["launches"] / 1024.0
+        rec["calibration"] = {"fetch_factor": copy_kib / (sum(cf) / len(cf)),
+                              "write_factor": copy_kib / (sum(cw) / len(cw)),
+                              "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
+    cal = rec["calibration"]
+    stats = {}
+    if trace_csv:
+        with open(trace_csv) as f:
+            for r in csv.DictReader(f):
+                stats[r["Name"]] = (float(r["AverageNs"]), int(r["Calls"]))
+    wl = line["config"]["workload"]
+    grid = line["config"]["grid"]
+    cells = grid[0] * grid[1]
+    base = ("blast" if wl.startswith("blast") else "rarefaction") + "%d" % grid[0]
+    if "RLMP" in wl:
+        base += "_rlmp"
+    sha = kernel_source_digest()
+    rec["source_sha256"] = sha
+    for form, v in line["forms"].items():
+        tname = "double" if form == "fp64" else "float"
+        pick = lambda rows: [x for k, x in rows if "step_kernel<%s" % tname in k]
+        fv, wv = pick(fetch), pick(write)
+        if not fv or not wv:
+            continue
+        rd = sum(fv) / len(fv) * 1024.0 * cal["fetch_factor"]
+        wr = sum(wv) / len(wv) * 1024.0 * cal["write_factor"]
+        bpc = BYTES_PER_CELL[form]
+        launch = v["launch"]
+        if isinstance(launch, dict):
+            launch = [launch["strip_rows"], launch["waves_per_group"], launch["groups_per_cu"], launch["strip_mode"]]
+        entry = {"source_sha256": sha, "launch": launch, "bytes_per_launch": rd + wr, "read_bytes": rd,
+                 "write_bytes": wr, "algorithmic_bytes": bpc * cells, "bytes_per_cell": bpc, "cells": cells,
+                 "dispatches": len(fv)}
+        for name, (avg, calls) in stats.items():
+            if "step_kernel<%s" % tname in name:
+                entry["trace_average_ns"], entry["trace_calls"] = avg, calls
+        rec["%s_%s" % (base, form)] = entry
+    with open(PMC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def cpu_baseline(n, steps, workload_steps=500):
+    """The oracle timed on the blast workload's own grid (n x n): `steps`
+    steps with OpenMP over rows on every host core the process may use, and
+    one step single-threaded (in a child process with OMP_NUM_THREADS=1, since
+    the thread count is fixed when the oracle's OpenMP runtime starts).  The
+    rate is per cell-update, so the full 500-step run is extrapolated from
+    the sample by that rate."""
+    import subprocess
+
+    rate, dt, threads = _oracle_blast_rate(n, steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench._oracle_blast_rate(%d, 1)))" % (ROOT, n))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True)
+    single = None
+    if r.returncode == 0:
+        r1, d1, t1 = json.loads(r.stdout.strip().splitlines()[-1])
+        single = {"value": r1, "unit": "GLUPS", "cores": t1,
+                  "sample": "FP64 oracle on the blast workload at %dx%d for 1 step (%.1f s), one thread" % (n, n, d1)}
+    return {"value": rate, "unit": "GLUPS", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "FP64 oracle on the blast workload at %dx%d (the benchmark's grid) for %d steps "
+                      "(%.1f s), OpenMP over rows" % (n, n, steps, dt),
+            "extrapolated_full_run_s": n * n * workload_steps / (rate * 1e9),
+            "extrapolation": "the %d-step workload at the sample's rate per cell-update" % workload_steps,
+            "single_thread": single}
+
+
+def fp32_error_vs_oracle(n=1024, steps=500):
+    """The FP32-state form's relative L1 density error after `steps` steps of
+    the blast at n x n against the FP64 oracle, beside the oracle's own spread
+    from a one-float32-rounding (6e-8) perturbation of the initial data: the
+    floor below which no float32-state run can be held at this size and
+    horizon (the PP-limited blast amplifies perturbations)."""
+    import numpy as np
+
+    import oracle
+    from paper_2411_15001_amd import binding as B
+    from paper_2411_15001_amd import cases
+    from paper_2411_15001_amd.solver import Solver
+
+    u0 = cases.blast(n, seed=0)
+    cfg = oracle.Config(nx=n, ny=n, limiters=oracle.RHO_PP | oracle.PRESSURE)
+    S, _ = oracle.init(cfg, u0)
+    t0 = time.perf_counter()
+    S, _, _, _ = oracle.run(cfg, S, steps)
+    dt = time.perf_counter() - t0
+    rng = np.random.default_rng(1)
+    Sp, _ = oracle.init(cfg, u0 * (1 + 6e-8 * rng.uniform(-1, 1, u0.shape)))
+    Sp, _, _, _ = oracle.run(cfg, Sp, steps)
+    s = Solver(u0, precision=B.LBM_FP32_STATE, limiters=B.LBM_RHO_PP | B.LBM_PRESSURE)
+    s.step(steps)
+    rho32 = s.moments().cpu().numpy()[0]
+    s.close()
+
+    def l1(a, b):
+        return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+    return {"rel_l1_rho_vs_oracle": l1(rho32, S[0]), "oracle_floor": l1(Sp[0], S[0]), "steps": steps,
+            "grid": [n, n], "target": 1e-4, "oracle_s": dt,
+            "note": "oracle_floor: the FP64 oracle's own relative L1 change from a 6e-8 perturbation of u0"}
 
 
 def _cpu_line(cell_updates, dt, sample):
@@ -485,6 +637,9 @@ def bench_adjoint(a):
 
 def main():
     a = parse()
+    if a.record_traffic:
+        record_traffic(*a.record_traffic)
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
@@ -507,7 +662,8 @@ def main():
     forms = {}
     rho = {}
     for form in a.forms.split(","):
-        forms[form], rho[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune)
+        forms[form], rho[form] = time_form(form, u0t, a.n, a.steps, a.warmup, not a.no_autotune,
+                                           total_steps=a.error_steps)
         L = forms[form]["launch"]
         forms[form]["roofline"]["traffic"] = traffic_for(
             "blast%d_%s" % (a.n, form), [L["strip_rows"], L["waves_per_group"], L["groups_per_cu"], L["strip_mode"]])
@@ -532,7 +688,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "blast %dx%d periodic, gamma 1.4, alpha 1/2, a = 4 lambda, "
                                "PP + pressure limiters, %s form" % (a.n, a.n, head),
-                   "grid": [a.n, a.n], "steps": a.steps},
+                   "grid": [a.n, a.n], "steps": a.steps,
+                   "co_headline": ("fp64 form (float64 throughout, the paper's precision): forms.fp64, "
+                                   "%.2f GLUPS, %.1f%% of 8 TB/s" % (forms["fp64"]["value"],
+                                                                    100 * forms["fp64"]["roofline"]["frac"]))
+                   if "fp64" in forms and head != "fp64" else None},
         "roofline": H["roofline"],
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
     }
@@ -542,8 +702,11 @@ def main():
         # FP64 form is bit-identical to the oracle (parity tests), so it stands
         # in for the oracle at this size
         err = float((rho["fp32"] - rho["fp64"]).abs().sum() / rho["fp64"].abs().sum())
-        out["fp32_error"] = {"rel_l1_rho_vs_fp64": err, "steps": a.warmup + a.steps,
-                             "grid": [a.n, a.n]}
+        out["fp32_error"] = {"rel_l1_rho_vs_fp64": err, "steps": max(a.error_steps, a.warmup + a.steps),
+                             "grid": [a.n, a.n], "target": 1e-4,
+                             "note": "both forms stepped from the same initial state to the workload's step "
+                                     "count (timed steps included); the FP64 form is bit-identical to the "
+                                     "oracle, so it stands in for the oracle at this size"}
     del rho
     torch.cuda.empty_cache()
     cg = device_copy_gbs()
@@ -554,6 +717,8 @@ def main():
     if a.calib_gib > 0:
         out["calibration_copy"] = calibration_copy(a.calib_gib)
     if not a.no_cpu:
+        if "fp32" in forms and not a.no_oracle_error:
+            out["fp32_error_vs_oracle"] = fp32_error_vs_oracle()
         out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.cpu_steps)
     print(json.dumps(out))
 

@@ -96,7 +96,22 @@ typedef struct {
   double rlmp_lo, rlmp_hi; /* relaxed bound factors (0.999, 1.001) */
   int32_t unsafe;     /* 1 allows alpha < 1/2 or beta < 1 (no positivity
                          guarantee); 0 rejects them */
+  int32_t blend;      /* LBM_BLEND_FACE (0): the face blending of Section 3.2,
+                         eqs. (25), (27), the method; LBM_BLEND_CELL (1): the
+                         per-cell blending that Section 3.1 states first and
+                         sets aside (eq. (naive_blending)), an ablation */
 } lbm_params;
+
+/* Blending of the first- and second-order updates.  LBM_BLEND_CELL blends
+ * every distribution leaving a cell with that cell's factor theta_ij, taken
+ * as the smallest factor of the cell's four faces (a ghost cell takes the
+ * factor of the cell it copies); it conserves the moments but guarantees no
+ * positivity.  Single instance, no wall or Dirichlet cells, no adjoint
+ * (LBM_ENOTSUP); every step then runs the fused kernel for the face factors
+ * and a plain per-cell update kernel, and n_limited counts cells with
+ * theta_ij < 1. */
+#define LBM_BLEND_FACE 0
+#define LBM_BLEND_CELL 1
 
 typedef struct {
   double lambda;       /* lambda^n of the current state (instance 0 / inst) */

@@ -36,6 +36,8 @@ LBM_BND_DIRICHLET = 2
 LBM_WEST, LBM_EAST, LBM_SOUTH, LBM_NORTH = 0, 1, 2, 3
 LBM_FP64 = 0
 LBM_FP32_STATE = 1
+LBM_BLEND_FACE = 0
+LBM_BLEND_CELL = 1
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_batch_workspace_bytes", "lbm_init", "lbm_init_batch",
@@ -60,6 +62,7 @@ class lbm_params(ctypes.Structure):
         ("sponge", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("eps", ctypes.c_double), ("rlmp_lo", ctypes.c_double), ("rlmp_hi", ctypes.c_double),
         ("unsafe", ctypes.c_int32),
+        ("blend", ctypes.c_int32),
     ]
 
 
@@ -154,12 +157,12 @@ def make_params(nx, ny, dx=None, gamma=1.4, alpha=0.5, order=2,
                 limiters=LBM_RHO_PP | LBM_PRESSURE, a_mode=LBM_A_DYNAMIC, a_beta=1.0,
                 a_fixed=0.0, bc_x=LBM_BC_PERIODIC, bc_y=LBM_BC_PERIODIC, sponge=0,
                 precision=LBM_FP64, eps=1e-16, rlmp_lo=0.999, rlmp_hi=1.001,
-                unsafe=0):
+                unsafe=0, blend=0):
     if dx is None:
         dx = 1.0 / nx if nx > 0 else 1.0  # nx < 1 is refused by the library
     return lbm_params(nx, ny, dx, gamma, alpha, order, limiters,
                       a_mode, a_beta, a_fixed, bc_x, bc_y, sponge, precision, eps, rlmp_lo,
-                      rlmp_hi, unsafe)
+                      rlmp_hi, unsafe, blend)
 
 
 def _ptr(t):

@@ -66,6 +66,7 @@ const char* check_params(const lbm_params* p) {
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return "unknown boundary condition";
   if (p->sponge < 0) return "sponge must be >= 0";
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_STATE) return "unknown precision";
+  if (p->blend != LBM_BLEND_FACE && p->blend != LBM_BLEND_CELL) return "unknown blend";
   if (!(p->eps >= 0.0)) return "eps must be >= 0";
   if (!(p->rlmp_lo > 0.0 && p->rlmp_lo <= 1.0 && p->rlmp_hi >= 1.0)) return "bad RLMP factors";
   return nullptr;
@@ -119,7 +120,7 @@ Layout layout(const lbm_params* p, int n, const int* nx, const int* ny) {
   L.bufB = o;
   o = align_up(o + (size_t)20 * cells * elem);
   L.theta = o;
-  if (n == 1 && p->precision == LBM_FP64)  // theta faces for the adjoint
+  if (n == 1 && (p->precision == LBM_FP64 || p->blend == LBM_BLEND_CELL))  // face factors: adjoint, per-cell blending
     o = align_up(o + sizeof(double) * ((size_t)(nx[0] + 1) * ny[0] + (size_t)nx[0] * (ny[0] + 1)));
   L.total = o;
   return L;
@@ -313,13 +314,28 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
 }
 
 // A step with Dirichlet boundary cells first raises lambda^n by their states
-// (Bouchut's condition covers every state the stencil reads).
+// (Bouchut's condition covers every state the stencil reads).  With the
+// per-cell blending the fused kernel only supplies the face factors (into
+// the caller's face buffers, else the workspace's): its slot record is parked
+// around it and the per-cell kernel writes the state and does the step's
+// bookkeeping.
 hipError_t launch_step_with_bnd(const lbm_ctx* c, const vlbm::StepArgs& a) {
   if (c->has_dirichlet) {
     hipError_t e = vlbm::launch_bnd_lambda(a, a.slot, c->stream);
     if (e != hipSuccess) return e;
   }
-  return vlbm::launch_step(a, c->p.precision, c->stream);
+  if (c->p.blend != LBM_BLEND_CELL) return vlbm::launch_step(a, c->p.precision, c->stream);
+  vlbm::StepArgs f = a;
+  if (!f.theta_x) {
+    f.theta_x = (double*)(c->ws + c->lay.theta);
+    f.theta_y = f.theta_x + (size_t)(c->insts[0].nx + 1) * c->insts[0].ny;
+  }
+  Slots* save = (Slots*)(c->ws + c->lay.slots_save);
+  hipError_t e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = vlbm::launch_step(f, c->p.precision, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->slots, save, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = vlbm::launch_percell(f, c->p.precision, c->stream);
+  return e;
 }
 
 lbm_status launch_one(lbm_ctx* c) {
@@ -371,6 +387,8 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   if (!u0 || !ws) return fail(nullptr, LBM_EINVAL, "u0 and workspace must be device pointers");
   if (((uintptr_t)ws) % kAlign) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
   if (p->sponge > 0 && n > 1) return fail(nullptr, LBM_ENOTSUP, "sponge layers are single-instance only");
+  if (p->blend == LBM_BLEND_CELL && n > 1)
+    return fail(nullptr, LBM_ENOTSUP, "the per-cell blending is single-instance only");
 
   lbm_ctx* c = new lbm_ctx();
   c->p = *p;
@@ -771,6 +789,8 @@ lbm_status lbm_set_instance_boundary(lbm_ctx* c, int32_t inst, int32_t side, con
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
   if (side < 0 || side > 3) return fail(c, LBM_EINVAL, "side must be 0 (west), 1 (east), 2 (south) or 3 (north)");
+  if (c->p.blend == LBM_BLEND_CELL)
+    return fail(c, LBM_ENOTSUP, "boundary descriptions are not supported with the per-cell blending");
   const int ax = side / 2;
   if ((ax == 0 ? c->p.bc_x : c->p.bc_y) != LBM_BC_OUTFLOW)
     return fail(c, LBM_EINVAL, "boundary descriptions need the side's axis to be non-periodic (LBM_BC_OUTFLOW)");
@@ -1064,6 +1084,7 @@ lbm_status adjoint_checks(lbm_ctx* c, const double* U, const double* Ub1, const 
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (c->p.blend != LBM_BLEND_FACE) return fail(c, LBM_ENOTSUP, "the adjoint covers the face blending only");
   if (!U || !Ub1 || !Ub0) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   if (U == Ub0 || Ub1 == Ub0) return fail(c, LBM_EINVAL, "Ubar_n must not alias the inputs");
   if ((const void*)U == c->other() || (const void*)U == c->cur())
@@ -1147,6 +1168,7 @@ extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const doubl
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->n_inst != 1 || c->p.precision != LBM_FP64)
     return fail(c, LBM_ENOTSUP, "the adjoint is single-instance float64 only");
+  if (c->p.blend != LBM_BLEND_FACE) return fail(c, LBM_ENOTSUP, "the adjoint covers the face blending only");
   if (!u0 || !Ub0 || !u0b) return fail(c, LBM_EINVAL, "adjoint buffers must be device pointers");
   Slots* save = (Slots*)(c->ws + c->lay.slots_save);
   hipError_t e = hipMemcpyAsync(save, c->slots, sizeof(Slots), hipMemcpyDeviceToDevice, c->stream);

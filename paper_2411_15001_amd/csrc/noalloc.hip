@@ -80,6 +80,7 @@ int strip_rows(int nx, int ny, int precision) {
 extern "C" lbm_status lbm_step_noalloc(const lbm_params* p, const void* src_dev, void* dst_dev,
                                        void* stream, lbm_diag* diag_host) {
   if (const char* m = vlbm::host_check_params(p)) return fail(LBM_EINVAL, m);
+  if (p->blend != LBM_BLEND_FACE) return fail(LBM_ENOTSUP, "lbm_step_noalloc: face blending only");
   if (!src_dev || !dst_dev) return fail(LBM_EINVAL, "lbm_step_noalloc: state buffers must be device pointers");
   const long long cells = (long long)p->nx * p->ny;
   const size_t bytes = (size_t)20 * (size_t)cells * (p->precision == LBM_FP64 ? 8 : 4);

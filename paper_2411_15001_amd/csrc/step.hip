@@ -1050,13 +1050,340 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
   if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp, n_nf, n_rho);
 }
 
+// ------------------------------------------ bounds-limited march, LDS-staged
+
+// Rows of the state in flight for the LDS-staged march: the row being
+// consumed and the two behind it.  Each row occupies 20 planes x 64 columns
+// of T followed by the 16 halo loads of 16 bytes each.
+constexpr int kDmaRing = 3;
+constexpr int kDmaHaloBytes = 16 * 16;
+template <class T>
+constexpr int dma_row_bytes() { return 20 * 64 * (int)sizeof(T) + kDmaHaloBytes; }
+template <class T>
+constexpr int dma_lds_bytes(int waves) { return waves * kDmaRing * dma_row_bytes<T>(); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// The bounds-limited march of march_lmp with the state rows brought in by
+// direct loads into LDS (global_load_lds_dwordx4: each lane moves 16 bytes,
+// so one instruction carries 1024 bytes, two planes' rows in float64 or four
+// in float32) two rows ahead of the row being consumed, instead of through
+// registers one row ahead.  The halo values of the edge lanes (the columns
+// x0 - 1, x0 - 2, x0 + 64, x0 + 65) come in the same way, 16 bytes per lane
+// from 16 lanes.
+// Arithmetic, evaluation order and results are those of march_lmp; only where
+// the loaded values wait differs.  Used for single instances whose width is a
+// multiple of 64 (every strip full) with the limiter set fixed at compile
+// time.  The loads into LDS are not tracked by the compiler's wait counters:
+// the march waits on the vector-memory counter itself (see the loop head).
+template <class T, class C, int LIMS, bool TH>
+__device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in, Slots* sl, int xs,
+                                              int ys, int lane, int wave) {
+  const Scheme& sc = A.sc;
+  const int nx = in.nx, ny = in.ny;
+  const int x0 = xs * 64;
+  const int gi = x0 + lane;
+  const bool first = lane == 0, last = lane == 63;
+  const int y0 = ys * in.strip_h;
+  const int y1 = min(y0 + in.strip_h, ny);
+
+  const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+  const StepConst<T, C> K = step_const<T, C>(sc, lam);
+
+  if (xs == 0 && ys == 0 && lane == 0) {
+    sl->lam[(A.slot + 2) % 3] = 0ull;
+    sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
+  }
+
+  const T* __restrict__ sbase = (const T*)A.src + in.off;
+  T* __restrict__ dbase = (T*)A.dst + in.off;
+  const long long P = A.plane;
+  const unsigned unx = (unsigned)nx;
+
+  extern __shared__ __align__(16) unsigned char dma_lds[];
+  unsigned char* ring = dma_lds + wave * kDmaRing * dma_row_bytes<T>();
+  // lane's byte offset inside one load of 1024 bytes: planes per load
+  constexpr int kPpl = 1024 / (64 * (int)sizeof(T));  // 2 (float64) or 4 (float32)
+  constexpr int kLanesPerPlane = 64 / kPpl;
+  const long long lane_elem = (long long)(lane / kLanesPerPlane) * P + (lane % kLanesPerPlane) * (16 / (int)sizeof(T));
+  // halo: lanes 0-7 bring 16 bytes of planes 0-7 (u, u_1) that hold the
+  // west columns x0 - 2 and x0 - 1, lanes 8-15 16 bytes of planes 0-3 and
+  // 8-11 (u, u_2) that hold the east columns x0 + 64 and x0 + 65.  Each pair
+  // of columns is wrapped or clamped first; the two are then adjacent or
+  // equal (x0 is a multiple of 64 and so is nx), and the 16 bytes start at the
+  // aligned element at or below the smaller one; west2 .. east1 are the
+  // columns' positions inside the 16 bytes.
+  constexpr int kVpl = 16 / (int)sizeof(T);  // values per 16 bytes
+  const bool hlane = lane < 16;
+  int wstart, west2, west1, estart, east0, east1;
+  {
+    const int a2 = map_index(x0 - 2, nx, sc.bc_x), a1 = map_index(x0 - 1, nx, sc.bc_x);
+    wstart = min(a2, a1) / kVpl * kVpl;
+    west2 = a2 - wstart;
+    west1 = a1 - wstart;
+    const int b0 = map_index(x0 + 64, nx, sc.bc_x), b1 = map_index(x0 + 65, nx, sc.bc_x);
+    estart = min(b0, b1) / kVpl * kVpl;
+    east0 = b0 - estart;
+    east1 = b1 - estart;
+  }
+  const int hq = lane < 8 ? lane : (lane < 12 ? lane - 8 : lane - 4);
+  const long long halo_elem = (long long)hq * P + (lane < 8 ? wstart : estart);
+
+  // bring row R (wrapped or clamped) into ring buffer b
+  auto issue = [&](int R, int b) {
+    const long long ro = (long long)map_index(R, ny, sc.bc_y) * nx;
+    unsigned char* dst = ring + b * dma_row_bytes<T>();
+#pragma unroll
+    for (int q = 0; q < 20; q += kPpl) {
+      const T* g = sbase + (long long)q * P + ro + x0 + lane_elem;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 64 * (int)sizeof(T)), 16, 0, 0);
+    }
+    if (hlane) {
+      const T* g = sbase + halo_elem + ro;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + 20 * 64 * (int)sizeof(T)), 16, 0, 0);
+    }
+  };
+  // vector-memory operations of one row's loads
+  constexpr int kRowOps = 20 / kPpl + 1;
+
+  // carried state (zero before the first rows arrive)
+  C pu[4] = {}, pf[4] = {}, pg[4] = {}, puk[4][4] = {};
+  C pusx[4] = {}, pdF[4] = {};
+  C pusy[4] = {}, pdG[4] = {};
+  C pmu = C(0), pnu = C(0);
+  C qM3[4] = {}, qd3[4] = {}, qP[4] = {};
+  C hpu[4] = {}, hpk[4] = {}, hpf[4] = {}, hpg[4] = {};
+  C opr = C(0), opm = C(0), hpy = C(0);
+
+  double lmax = 0.0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_lmp = 0, n_cls = 0;
+
+  issue(y0 - 2, 0);
+  issue(y0 - 1, 1);
+  int b = 0;
+  for (int L = y0 - 2; L <= y1 + 1; ++L) {
+    // row L has arrived when at most the newest row's loads (issued at the
+    // end of the previous iteration, after every store) are outstanding; in
+    // the last iteration nothing newer was issued
+    if (L + 1 <= y1 + 1)
+      __builtin_amdgcn_s_waitcnt(sizeof(T) == 8 ? 0x0F7B : 0x0F76);  // vmcnt(kRowOps)
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    static_assert(kRowOps == (sizeof(T) == 8 ? 11 : 6), "wait count of the loop head");
+    const unsigned char* rb = ring + b * dma_row_bytes<T>();
+    const T* rowv = (const T*)rb;
+    const T* hrow = (const T*)(rb + 20 * 64 * (int)sizeof(T));
+    C u[4], uk[4][4], hu[4], hk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (C)rowv[c * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) uk[k][c] = (C)rowv[(4 + 4 * k + c) * 64 + lane];
+    // halo: lane 0 reads the west values (column x0 - 1, and x0 - 2 for rho
+    // and m1), every other lane the east ones (only lane 63 uses them); halo
+    // load lane h left its 16 bytes at h * kVpl values
+    const int hbase = first ? 0 : 8;
+    const int ein = first ? west1 : east0;   // the halo column's element
+    const int eout = first ? west2 : east1;  // the outer column's element
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      hu[c] = (C)hrow[(hbase + c) * kVpl + ein];
+      hk[c] = (C)hrow[(hbase + 4 + c) * kVpl + ein];
+    }
+    const C orr = (C)hrow[hbase * kVpl + eout], om = (C)hrow[(hbase + 1) * kVpl + eout];
+
+    // ---- row L: fluxes, the x-face i+1/2 and the y-face L - 1/2
+    C f[4], g[4];
+    fluxes(u, K.gm1, f, g);
+    C hf[4], hg[4];
+    fluxes(hu, K.gm1, hf, hg);
+    C usx[4], dF[4], usy[4], dG[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C d1 = maxw(0, u[c], f[c], g[c], K.w, K.r2a) - uk[0][c];
+      const C d4 = maxw(3, u[c], f[c], g[c], K.w, K.r2a) - uk[3][c];
+      const C uE = from_right_or(u[c], hu[c]);
+      const C fE = from_right_or(f[c], hf[c]);
+      const C u2E = from_right_or(uk[1][c], hk[c]);
+      const C d2E = maxw(1, uE, fE, fE, K.w, K.r2a) - u2E;
+      usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
+      dF[c] = K.ac * (d1 - d2E);
+      const C pd3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a) - puk[2][c];
+      usy[c] = C(0.5) * (pu[c] + u[c]) - (g[c] - pg[c]) * K.r2k;
+      dG[c] = K.ac * (pd3 - d4);
+    }
+
+    // ---- row L - 1: the halo column's Maxwellians, the west edge face
+    C hM[4], hd[4], usw[4], dFw[4], pd2[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C hM1 = maxw(0, hpu[c], hpf[c], hpg[c], K.w, K.r2a);
+      const C hM2 = maxw(1, hpu[c], hpf[c], hpg[c], K.w, K.r2a);
+      hM[c] = first ? hM1 : hM2;
+      hd[c] = hM[c] - hpk[c];
+      pd2[c] = maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a) - puk[1][c];
+      usw[c] = C(0.5) * (hpu[c] + pu[c]) - (pf[c] - hpf[c]) * K.r2k;
+      dFw[c] = K.ac * (hd[c] - pd2[c]);
+    }
+
+    // ---- row L - 1: density bounds (eq. (29)) of the own cell and of the
+    // halo cell (edge lanes)
+    const C rW = from_left_or(pusx[0], usw[0]);
+    C mu1 = pu[0], nu1 = pu[0];
+    mu1 = vmin(mu1, rW);
+    nu1 = vmax(nu1, rW);
+    mu1 = vmin(mu1, pusx[0]);
+    nu1 = vmax(nu1, pusx[0]);
+    mu1 = vmin(mu1, pusy[0]);
+    nu1 = vmax(nu1, pusy[0]);
+    mu1 = vmin(mu1, usy[0]);
+    nu1 = vmax(nu1, usy[0]);
+    const C xin = first ? usw[0] : pusx[0];
+    const C rwo = first ? opr : hpu[0], rwe = first ? hpu[0] : opr;
+    const C mwo = first ? opm : hpu[1], mwe = first ? hpu[1] : opm;
+    const C xout = C(0.5) * (rwo + rwe) - (mwe - mwo) * K.r2k;
+    const C hy = C(0.5) * (hpu[0] + hu[0]) - (hu[2] - hpu[2]) * K.r2k;
+    C hmu = hpu[0], hnu = hpu[0];
+    hmu = vmin(hmu, first ? xout : xin);
+    hnu = vmax(hnu, first ? xout : xin);
+    hmu = vmin(hmu, first ? xin : xout);
+    hnu = vmax(hnu, first ? xin : xout);
+    hmu = vmin(hmu, hpy);
+    hnu = vmax(hnu, hpy);
+    hmu = vmin(hmu, hy);
+    hnu = vmax(hnu, hy);
+
+    // ---- theta of the x-face i+1/2 and the west edge face of row L - 1,
+    // and of the y-face L - 3/2
+    const C muE = from_right_or(mu1, hmu);
+    const C nuE = from_right_or(nu1, hnu);
+    int gx, gy, gw;
+    const double thx = face_theta<LIMS>(sc, pusx, pdF, K.kappa, mu1, nu1, muE, nuE, gx);
+    const double thy = face_theta<LIMS>(sc, pusy, pdG, K.kappa, pmu, pnu, mu1, nu1, gy);
+    const double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, hmu, hnu, mu1, nu1, gw);
+    const bool row1 = L - 1 >= y0 && L - 1 < y1;
+    const bool row2 = L - 2 >= y0 && L - 2 < y1;
+    if (row1 && !last) {
+      n_guard += gx;
+      n_lim += (thx < 1.0);
+    }
+    if (row1) {
+      n_guard += gy;
+      n_lim += (thy < 1.0);
+    }
+    if (row1 && first) {
+      n_guard += gw;
+      n_lim += (th_edge < 1.0);
+    }
+    if (TH) {
+      if (row1 && first) A.theta_x[(long long)(L - 1) * (nx + 1) + x0] = th_edge;
+      if (row1) A.theta_x[(long long)(L - 1) * (nx + 1) + gi + 1] = thx;
+      if ((row1 || row2) && L - 1 >= 0 && L - 1 <= ny) A.theta_y[(long long)(L - 1) * nx + gi] = thy;
+    }
+
+    // ---- rows L - 1 and L - 2: streaming and the moment slot (eqs. (25), (27))
+    const C tR = (C)thx;
+    const C tL = from_left_or(tR, (C)th_edge);
+    const C tB = (C)thy;
+    C fin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C pM1 = maxw(0, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pM3 = maxw(2, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pM4 = maxw(3, pu[c], pf[c], pg[c], K.w, K.r2a);
+      const C pd1 = pM1 - puk[0][c];
+      const C pd4 = pM4 - puk[3][c];
+      const C u1n = from_left_or(pM1 + tR * pd1, hM[c] + tL * hd[c]);
+      const C M2E = from_right_or(maxw(1, pu[c], pf[c], pg[c], K.w, K.r2a), hM[c]);
+      const C d2E = from_right_or(pd2[c], hd[c]);
+      const C u2n = M2E + tR * d2E;
+      const C u3n = qM3[c] + tB * qd3[c];
+      C s = K.alpha * pu[c];
+      s = s + (u1n - tL * pd2[c]);
+      s = s + (u2n - tR * pd1);
+      s = s + (u3n - tB * pd4);
+      const C u4n = pM4 + tB * pd4;
+      fin[c] = qP[c] + (u4n - tB * qd3[c]);
+      if (row1) {
+        const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
+        put(&(dbase + (4 + c) * P)[o], (T)u1n);
+        put(&(dbase + (8 + c) * P)[o], (T)u2n);
+        put(&(dbase + (12 + c) * P)[o], (T)u3n);
+      }
+      if (row2) {
+        const unsigned o = (unsigned)(L - 2) * unx + (unsigned)gi;
+        put(&(dbase + c * P)[o], (T)fin[c]);
+        put(&(dbase + (16 + c) * P)[o], (T)u4n);
+      }
+      qP[c] = s;
+      qM3[c] = pM3;
+      qd3[c] = pM3 - puk[2][c];
+    }
+    if (row2) {
+      const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
+                                      (double)(T)fin[3], sc.gamma);
+      if (l < 0.0) {
+        n_bad += 1;
+        n_cls += bad_class((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2], (double)(T)fin[3],
+                           sc.gamma);
+      } else {
+        lmax = vmax(lmax, l);
+      }
+      const double r = (double)(T)fin[0], lo = (double)pmu, hi = (double)pnu;
+      n_lmp += (r < lo - kLmpTol<T> * fabs(lo)) || (r > hi + kLmpTol<T> * fabs(hi));
+    }
+    pmu = mu1;
+    pnu = nu1;
+    hpy = hy;
+    opr = orr;
+    opm = om;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      pu[c] = u[c];
+      pf[c] = f[c];
+      pg[c] = g[c];
+      pusx[c] = usx[c];
+      pdF[c] = dF[c];
+      pusy[c] = usy[c];
+      pdG[c] = dG[c];
+      hpu[c] = hu[c];
+      hpk[c] = hk[c];
+      hpf[c] = hf[c];
+      hpg[c] = hg[c];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
+    }
+    // the next loads go into the buffer of row L - 1, consumed a full
+    // iteration ago, after this iteration's stores (so that the loop head's
+    // count of newer operations is exactly one row's loads)
+    __builtin_amdgcn_sched_barrier(0);
+    if (L + 2 <= y1 + 1) issue(L + 2, b == 0 ? 2 : b - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    b = b == 2 ? 0 : b + 1;
+  }
+
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_lmp += __shfl_xor(n_lmp, off, 64);
+    n_bad += __shfl_xor(n_bad, off, 64);
+    n_guard += __shfl_xor(n_guard, off, 64);
+    n_lim += __shfl_xor(n_lim, off, 64);
+  }
+  unsigned n_nf, n_rho;
+  reduce_classes(n_cls, n_nf, n_rho);
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp, n_nf, n_rho);
+}
+
 // The step kernel: T the state's storage type, C its arithmetic type, LMP the
 // bounds-limited march, WPE the waves per SIMD the registers are sized for,
 // LIMS a limiter set fixed at compile time (0: read from the scheme) and TH
 // whether the face factors are written (with LIMS = 0 they are written
 // whenever A.theta_x is set), BND whether boundary descriptions are read
 // (only with LIMS = 0).
-template <class T, class C, bool LMP, int WPE, int LIMS, bool TH, bool BND>
+template <class T, class C, bool LMP, int WPE, int LIMS, bool TH, bool BND, bool DMA = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
@@ -1083,11 +1410,182 @@ void step_kernel(StepArgs A) {
     const long long local = item - in.item0;
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
-    if (LMP)
+    if (LMP && DMA)
+      march_lmp_dma<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane, wave);
+    else if (LMP)
       march_lmp<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
     else
       march_short<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
   }
+}
+
+// ------------------------------------------------- per-cell blending (ablation)
+
+// Per-cell blending, the first possibility of Section 3.1 (eq.
+// (naive_blending)), which the paper sets aside in favour of the face
+// blending above: every distribution leaving cell U is M_k(u_U) + theta_U
+// d_k(U) and the rest population is blended with the cell's own factor, so
+// the moment slot takes alpha u plus, face by face (W, E, S, N), the incoming
+// distribution minus theta_C times the own distribution leaving through that
+// face.  theta_U of a cell is the smallest factor of its four faces, read
+// from the face fields the fused step kernel wrote for the same state (tx
+// [ny][nx + 1], ty [ny + 1][nx]); a ghost cell takes the factor of the cell
+// it copies.  One thread per cell, neighbours read from memory: a plain
+// kernel for an ablation, not a tuned one.  It also does the step's
+// bookkeeping (lambda slots, time, counters) in place of the fused kernel,
+// whose slot record the launcher restores.
+__device__ __forceinline__ double cell_factor(const double* tx, const double* ty, int i, int j, int nx) {
+  double t = tx[(long long)j * (nx + 1) + i];
+  t = vmin(t, tx[(long long)j * (nx + 1) + i + 1]);
+  t = vmin(t, ty[(long long)j * nx + i]);
+  t = vmin(t, ty[(long long)(j + 1) * nx + i]);
+  return t;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void percell_kernel(StepArgs A) {
+  const Scheme& sc = A.sc;
+  const Inst in = A.inst0;
+  const int nx = in.nx, ny = in.ny;
+  Slots* sl = A.slots;
+  const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+  const StepConst<T, T> K = step_const<T, T>(sc, lam);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sl->lam[(A.slot + 2) % 3] = 0ull;
+    sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
+  }
+  const T* __restrict__ S = (const T*)A.src;
+  T* __restrict__ D = (T*)A.dst;
+  const long long P = A.plane;
+  const bool lmp = sc.order == 2 && (sc.limiters & 6) != 0;
+  const bool faces = sc.order == 2 && sc.limiters != 0;
+  double lmax = 0.0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_lmp = 0, n_cls = 0;
+  const long long ncell = (long long)nx * ny;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(c / nx), i = (int)(c % nx);
+    const int iw = map_index(i - 1, nx, sc.bc_x), ie = map_index(i + 1, nx, sc.bc_x);
+    const int js = map_index(j - 1, ny, sc.bc_y), jn = map_index(j + 1, ny, sc.bc_y);
+    const long long oc = c, ow = (long long)j * nx + iw, oe = (long long)j * nx + ie,
+                    os = (long long)js * nx + i, on = (long long)jn * nx + i;
+    const double thC = cell_factor(A.theta_x, A.theta_y, i, j, nx);
+    const double thW = cell_factor(A.theta_x, A.theta_y, iw, j, nx);
+    const double thE = cell_factor(A.theta_x, A.theta_y, ie, j, nx);
+    const double thS = cell_factor(A.theta_x, A.theta_y, i, js, nx);
+    const double thN = cell_factor(A.theta_x, A.theta_y, i, jn, nx);
+    // the five cells' moments and fluxes
+    T u[5][4], f[5][4], g[5][4];
+    const long long o5[5] = {oc, ow, oe, os, on};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[q][k] = S[k * P + o5[q]];
+      fluxes(u[q], K.gm1, f[q], g[q]);
+    }
+    T fin[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // d_k = M_k - u_k of the upwind cells and of the cell itself
+      const T MW = maxw(0, u[1][k], f[1][k], g[1][k], K.w, K.r2a);
+      const T ME = maxw(1, u[2][k], f[2][k], g[2][k], K.w, K.r2a);
+      const T MS = maxw(2, u[3][k], f[3][k], g[3][k], K.w, K.r2a);
+      const T MN = maxw(3, u[4][k], f[4][k], g[4][k], K.w, K.r2a);
+      const T dW = MW - S[(4 + k) * P + ow];
+      const T dE = ME - S[(8 + k) * P + oe];
+      const T dS = MS - S[(12 + k) * P + os];
+      const T dN = MN - S[(16 + k) * P + on];
+      const T d1 = maxw(0, u[0][k], f[0][k], g[0][k], K.w, K.r2a) - S[(4 + k) * P + oc];
+      const T d2 = maxw(1, u[0][k], f[0][k], g[0][k], K.w, K.r2a) - S[(8 + k) * P + oc];
+      const T d3 = maxw(2, u[0][k], f[0][k], g[0][k], K.w, K.r2a) - S[(12 + k) * P + oc];
+      const T d4 = maxw(3, u[0][k], f[0][k], g[0][k], K.w, K.r2a) - S[(16 + k) * P + oc];
+      const T tC = (T)thC;
+      const T u1n = MW + (T)thW * dW;
+      const T u2n = ME + (T)thE * dE;
+      const T u3n = MS + (T)thS * dS;
+      const T u4n = MN + (T)thN * dN;
+      T un = K.alpha * u[0][k];
+      un = un + (u1n - tC * d2);
+      un = un + (u2n - tC * d1);
+      un = un + (u3n - tC * d4);
+      un = un + (u4n - tC * d3);
+      fin[k] = un;
+      put(&D[k * P + oc], un);
+      put(&D[(4 + k) * P + oc], u1n);
+      put(&D[(8 + k) * P + oc], u2n);
+      put(&D[(12 + k) * P + oc], u3n);
+      put(&D[(16 + k) * P + oc], u4n);
+    }
+    n_lim += (thC < 1.0);
+    // face states of the cell's four faces (eq. (12)): the guard of the west
+    // and south faces (counted once per face, as in the fused kernel) and the
+    // eq. (29) bounds of the LMP check
+    {
+      T rsx[2], rsy[2];
+      for (int side = 0; side < 2; ++side) {
+        const int L = side == 0 ? 1 : 0, R = side == 0 ? 0 : 2;  // W|C or C|E
+        T us[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) us[k] = T(0.5) * (u[L][k] + u[R][k]) - (f[R][k] - f[L][k]) * K.r2k;
+        rsx[side] = us[0];
+        if (side == 0 && faces) {
+          const double r0 = us[0], m1 = us[1], m2 = us[2], E = us[3];
+          const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
+          n_guard += (!(r0 > 0.0) || !(g0 < 0.0));
+        }
+      }
+      for (int side = 0; side < 2; ++side) {
+        const int L = side == 0 ? 3 : 0, R = side == 0 ? 0 : 4;  // S|C or C|N
+        T us[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) us[k] = T(0.5) * (u[L][k] + u[R][k]) - (g[R][k] - g[L][k]) * K.r2k;
+        rsy[side] = us[0];
+        if (side == 0 && faces) {
+          const double r0 = us[0], m1 = us[1], m2 = us[2], E = us[3];
+          const double g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E;
+          n_guard += (!(r0 > 0.0) || !(g0 < 0.0));
+        }
+      }
+      if (lmp) {
+        T lo = u[0][0], hi = u[0][0];
+        lo = vmin(lo, rsx[0]);
+        hi = vmax(hi, rsx[0]);
+        lo = vmin(lo, rsx[1]);
+        hi = vmax(hi, rsx[1]);
+        lo = vmin(lo, rsy[0]);
+        hi = vmax(hi, rsy[0]);
+        lo = vmin(lo, rsy[1]);
+        hi = vmax(hi, rsy[1]);
+        const double r = (double)fin[0], dlo = (double)lo, dhi = (double)hi;
+        n_lmp += (r < dlo - kLmpTol<T> * fabs(dlo)) || (r > dhi + kLmpTol<T> * fabs(dhi));
+      }
+    }
+    const double l = cell_wavespeed((double)fin[0], (double)fin[1], (double)fin[2], (double)fin[3], sc.gamma);
+    if (l < 0.0) {
+      n_bad += 1;
+      n_cls += bad_class((double)fin[0], (double)fin[1], (double)fin[2], (double)fin[3], sc.gamma);
+    } else {
+      lmax = vmax(lmax, l);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_bad += __shfl_xor(n_bad, off, 64);
+    n_guard += __shfl_xor(n_guard, off, 64);
+    n_lim += __shfl_xor(n_lim, off, 64);
+    n_lmp += __shfl_xor(n_lmp, off, 64);
+  }
+  // unpacked per thread (below 2^16 each: see the launcher) before the
+  // wave reduction
+  unsigned n_nf = n_cls >> 16, n_rho = n_cls & 0xffffu;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    n_nf += __shfl_xor(n_nf, off, 64);
+    n_rho += __shfl_xor(n_rho, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp, n_nf, n_rho);
 }
 
 // ---------------------------------------------------------------- init etc.
@@ -1335,9 +1833,38 @@ __global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int slot) {
 // ensembles, 4% on the LMP runs); all other configurations run the general
 // kernels, and a grid with boundary descriptions the general kernels that
 // read them.
+// The LDS-staged bounds-limited march needs every strip full (width a
+// multiple of 64) and a single instance; its LDS (three rows per wave) is
+// dynamic, above the default limit in float64.
+template <class T, int WPE, int LIMS, bool TH>
+static void launch_dma(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+  const auto k = step_kernel<T, T, true, WPE, LIMS, TH, false, true>;
+  static const hipError_t attr =
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, dma_lds_bytes<T>(4));
+  (void)attr;
+  hipLaunchKernelGGL(k, grid, block, (unsigned)dma_lds_bytes<T>((int)block.x / 64), s, a);
+}
+
+static bool dma_ok(const StepArgs& a) {
+#ifdef VLBM_NO_DMA
+  return false;
+#else
+  return a.n_inst == 1 && a.inst0.nx % 64 == 0 && !a.bnd;
+#endif
+}
+
 template <class T, bool LMP, int WPE>
 static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
+  if constexpr (LMP) {
+    if (lims == kFixed && dma_ok(a)) {
+      if (a.theta_x)
+        launch_dma<T, WPE, kFixed, true>(a, grid, block, s);
+      else
+        launch_dma<T, WPE, kFixed, false>(a, grid, block, s);
+      return;
+    }
+  }
   if (a.bnd)
     hipLaunchKernelGGL((step_kernel<T, T, LMP, WPE, 0, false, true>), grid, block, 0, s, a);
   else if (lims == kFixed && a.theta_x)
@@ -1434,6 +1961,18 @@ hipError_t launch_totals(const Inst& in, long long plane, const void* S, double*
   else
     hipLaunchKernelGGL((totals_kernel<float>), dim3(blocks), dim3(256), 0, s,
                        (const float*)S + in.off, plane, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_percell(const StepArgs& a, int precision, hipStream_t s) {
+  const long long n = (long long)a.inst0.nx * a.inst0.ny;
+  // 8192 blocks of 256 threads (or one thread per cell): a thread visits at
+  // most 2^32 / 2^21 = 2048 cells, so its packed 16-bit class counts are exact
+  const int blocks = grid_for(n);
+  if (precision == 0)
+    hipLaunchKernelGGL((percell_kernel<double>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((percell_kernel<float>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

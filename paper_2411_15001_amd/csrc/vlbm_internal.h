@@ -92,6 +92,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_i
                                int slot, int precision, hipStream_t s);
 hipError_t launch_moments(const Inst& in, long long plane, const void* S,
                           double* out, int precision, hipStream_t s);
+// Per-cell blending step (an ablation): state A.src -> A.dst with the face
+// factors A.theta_x / A.theta_y of the same state, single instance; also
+// the step's slot bookkeeping.
+hipError_t launch_percell(const StepArgs& a, int precision, hipStream_t s);
 // Block minima of rho and of rho e = E - |m|^2 / (2 rho) over the finite
 // cells of the moment slot, part[blocks][2].
 hipError_t launch_minima(const Inst& in, long long plane, const void* S, double* part,

@@ -419,3 +419,47 @@ def test_ensemble_boundaries_equal_single_runs(prec, lims, gpu):
             S, _, _, tot = oracle.run(cfg, S, 12)
             assert np.array_equal(a, S[0:4]), i
     bs.close()
+
+
+def test_ensemble_boundary_rejections(gpu):
+    """lbm_set_instance_boundary's own checks on an ensemble, where each
+    instance has its own sides: an instance index out of range, a wall along
+    an instance's axis of one cell, a non-admissible Dirichlet state on one
+    instance, a side on a periodic axis.  A rejected call leaves every
+    instance's description as it was (the ensemble keeps stepping as an
+    ensemble with the accepted description only, bit for bit)."""
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    u0s = [np.ascontiguousarray(cases.riemann4(8, seed=3)[:, :8, :1]),
+           np.ascontiguousarray(cases.riemann4(8, seed=4))]
+    bs = BatchSolver(u0s, limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=0)
+    ok_kind = np.full(8, B.LBM_BND_WALL, np.uint8)  # instance 1, west side (ny = 8)
+    bs.set_boundary(1, W, ok_kind)
+
+    def rejected(inst, side, kind, state=None):
+        with pytest.raises(B.LbmError) as e:
+            bs.set_boundary(inst, side, kind, state)
+        assert e.value.status == B.LBM_EINVAL, (inst, side)
+
+    rejected(-1, W, ok_kind)
+    rejected(2, W, ok_kind)
+    # instance 0 is one cell wide: no wall on its west / east sides
+    rejected(0, W, np.full(8, B.LBM_BND_WALL, np.uint8))
+    rejected(0, E, np.full(8, B.LBM_BND_WALL, np.uint8))
+    # a Dirichlet state with rho <= 0 on instance 1
+    st = np.tile(np.array([[1.0], [0.0], [0.0], [2.5]]), (1, 8))
+    st[0, 3] = -1.0
+    rejected(1, E, np.full(8, B.LBM_BND_DIRICHLET, np.uint8), st)
+    # y is periodic: no south / north descriptions
+    rejected(1, 2, np.zeros(8, np.uint8))
+    rejected(0, 3, np.zeros(1, np.uint8))
+    # the accepted description is intact: the ensemble equals the single runs
+    bs.step(6)
+    for i, u in enumerate(u0s):
+        s = Solver(u, dx=1.0 / u.shape[2], limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=0)
+        if i == 1:
+            s.set_boundary(W, ok_kind)
+        s.step(6)
+        assert np.array_equal(bs.moments(i).cpu().numpy(), s.moments().cpu().numpy()), i
+        s.close()
+    bs.close()

@@ -188,61 +188,171 @@ def test_fixed_limiter_kernels(prec, lims):
     b.close()
 
 
-def test_table1_on_gpu():
-    """Section 4.1 at dx = 1/20 (PP and LMP, fixed a = 10.7, 214 steps): the
-    GPU reproduces the oracle bit for bit and hence Table 1's digits."""
-    n = 20
-    u0 = cases.entropy_wave(n)
-    for lims, ref in ((1 | 8, (3.23472e-3, 3.57255e-3, 4.57474e-3)),
-                      (2 | 8, (6.90503e-3, 7.74117e-3, 1.21124e-2))):
-        ocfg = oracle.Config(nx=n, ny=n, limiters=lims, a_mode=1, a_fixed=10.7)
+# widths that are multiples of 64 take the LDS-staged bounds-limited march
+# (PP + LMP + pressure, single instance); heights, strip heights, grids and
+# boundaries vary the ring's prologue and tail
+LDS_CASES = [
+    # nx, ny, bc_x, bc_y, strip rows, waves, groups per CU, precision
+    (64, 1, 1, 1, 4, 1, 0, B.LBM_FP64),
+    (64, 3, 0, 0, 4, 4, 0, B.LBM_FP64),
+    (128, 70, 1, 1, 16, 4, 0, B.LBM_FP64),
+    (192, 37, 0, 1, 64, 2, 0, B.LBM_FP64),
+    (256, 130, 1, 0, 8, 4, 1, B.LBM_FP64),
+    (128, 64, 1, 1, 4096, 1, 0, B.LBM_FP64),
+    (64, 5, 1, 1, 4, 4, 0, B.LBM_FP32_STATE),
+    (192, 99, 1, 1, 32, 4, 0, B.LBM_FP32_STATE),
+    (256, 64, 0, 0, 16, 2, 2, B.LBM_FP32_STATE),
+]
+
+
+@pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: "%dx%d-bc%d%d-h%d-w%d-g%d-p%d" % c)
+def test_lds_staged_lmp_march(case, gpu):
+    """The LDS-staged bounds-limited march (rows brought two ahead by direct
+    loads into LDS) against the register-staged one: the same states,
+    counters and face factors bit for bit, and in float64 the oracle's."""
+    nx, ny, bx, by, rows, waves, gpc, prec = case
+    u0 = np.ascontiguousarray(cases.riemann4(max(nx, ny), seed=nx + ny)[:, :ny, :nx])
+    ocfg = oracle.Config(nx=nx, ny=ny, limiters=1 | 2 | 8, a_beta=1.1, bc_x=bx, bc_y=by)
+    a = Solver(u0, precision=prec, **okw(ocfg))
+    a.set_launch(rows, waves, groups_per_cu=gpc)
+    # the register-staged march: an ensemble (two copies) takes it
+    kw = okw(ocfg)
+    kw.pop("dx")
+    b = BatchSolver([u0, u0], precision=prec, dx=[1.0 / nx] * 2, **kw)
+    steps = 12
+    for k in range(steps):
+        if k % 4 == 3:
+            tx, ty = a.step_theta()
+        else:
+            a.step(1)
+    b.step(steps)
+    G = a.get_state().cpu().numpy()
+    da = a.diagnostics()
+    ma = a.moments().cpu().numpy()
+    a.close()
+    db = b.diagnostics(0)  # before moments(), which clears the counters
+    for i in range(2):
+        assert np.array_equal(ma, b.moments(i).cpu().numpy()), i
+    for k in ("n_guard", "n_limited", "n_bad", "n_lmp", "lam"):
+        assert da[k] == db[k], (k, da[k], db[k])
+    b.close()
+    if prec == B.LBM_FP64:
         S, _ = oracle.init(ocfg, u0)
-        S, _, _, _ = oracle.run(ocfg, S, 214)
-        s = Solver(u0, **okw(ocfg))
-        s.step(214)
-        G = s.get_state().cpu().numpy()
-        assert np.array_equal(G, S)
-        e = G[0] - u0[0]
-        l1 = np.abs(e).sum() / np.abs(u0[0]).sum()
-        l2 = math.sqrt((e * e).sum() / (u0[0] ** 2).sum())
-        li = np.abs(e).max() / np.abs(u0[0]).max()
-        for v, r in zip((l1, l2, li), ref):
-            assert float("%.5e" % v) == r
-        s.close()
+        S, _, _, tot = oracle.run(ocfg, S, steps - 1)
+        S, otx, oty, info = oracle.step(ocfg, S)
+        assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
+        assert np.array_equal(tx.cpu().numpy(), otx) and np.array_equal(ty.cpu().numpy(), oty)
+        tot = np.array(tot) + (info.n_guard, info.n_limited, info.n_bad, info.n_lmp)
+        assert [da["n_guard"], da["n_limited"], da["n_bad"], da["n_lmp"]] == tot.tolist()
 
 
-def test_c1_full_size(tmp_path):
+def _table1():
+    import os
+
+    rows = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_entropy_wave.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, n, l1, l2, li = line.split()
+        rows[(name, int(n))] = (float(l1), float(l2), float(li))
+    return rows
+
+
+TABLE1_LIMS = {"PP": 1 | 8, "LMP": 2 | 8, "RLMP": 4 | 8}
+
+
+@pytest.mark.parametrize("n", [20, 40, 80, 160, 320, 640])
+@pytest.mark.parametrize("lim", ["PP", "LMP", "RLMP"])
+def test_table1_on_gpu(lim, n):
+    """Section 4.1, Table 1 on the GPU: the entropy wave with a fixed kinetic
+    speed a = 10.7 to t = 1 (10.7/dx steps) with the pressure limiter and each
+    density limiter, at every printed resolution.  The relative L1, L2 and Linf
+    errors of the density match every printed digit (PP and LMP), and the L1
+    and L2 columns of RLMP; the RLMP Linf column is not reproduced by the
+    definition that reproduces the other two sub-tables to every digit, so the
+    measured value is printed and bounded.  The LMP rows at dx = 1/320 and
+    1/640 agree to 3-4 digits (bounded below).  Up to dx = 1/320 the GPU state
+    also equals the oracle's bit for bit."""
+    ref = _table1()[(lim, n)]
+    u0 = cases.entropy_wave(n)
+    steps = int(round(10.7 * n))
+    ocfg = oracle.Config(nx=n, ny=n, limiters=TABLE1_LIMS[lim], a_mode=1, a_fixed=10.7)
+    s = Solver(u0, **okw(ocfg))
+    s.step(steps)
+    d = s.diagnostics()
+    G = s.get_state().cpu().numpy()
+    s.close()
+    assert abs(d["t"] - 1.0) < 1e-12
+    if lim == "PP":
+        assert d["n_limited"] == 0  # theta = 1 on every face and step (Section 4.1)
+    if n <= 320:
+        S, _ = oracle.init(ocfg, u0)
+        S, _, _, _ = oracle.run(ocfg, S, steps)
+        assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
+    e = G[0] - u0[0]
+    l1 = np.abs(e).sum() / np.abs(u0[0]).sum()
+    l2 = math.sqrt((e * e).sum() / (u0[0] ** 2).sum())
+    li = np.abs(e).max() / np.abs(u0[0]).max()
+    print("Table 1 %s 1/%d: L1 %.5e L2 %.5e Linf %.5e (printed %s)" % (lim, n, l1, l2, li, ref))
+    got = (l1, l2, li)
+    if lim == "LMP" and n >= 320:
+        # the LMP factor jumps where Delta F^rho changes sign at the wave's
+        # extrema, so rounding-level differences of evaluation order move
+        # these finest rows: measured 3.4e-4 (1/320) and 3.2e-3 (1/640) at
+        # most, relative
+        tol = 5e-4 if n == 320 else 4e-3
+        for v, r in zip(got, ref):
+            assert abs(v - r) <= tol * r, (v, r)
+        return
+    assert float("%.5e" % l1) == ref[0] and float("%.5e" % l2) == ref[1]
+    if lim != "RLMP":
+        assert float("%.5e" % li) == ref[2]
+    else:
+        assert li <= 1.3 * ref[2]
+
+
+def test_c1_full_size(tmp_path, capsys):
     """2048^2 near-vacuum double rarefaction, PP + LMP + pressure, a = 4
     lambda^n, outflow, in the benchmark's launch shape (from a copy of the
-    committed autotune cache): the first steps equal the oracle bit for bit at
-    full size, and 1000 steps stay admissible with every new density inside
-    its LMP bounds."""
+    committed autotune cache): after the workload's 1000 steps the state equals
+    the oracle's bit for bit (the oracle runs on the host's cores meanwhile,
+    about three minutes, printing its progress), every step stayed admissible
+    and every new density inside its LMP bounds."""
     import os
     import shutil
+    import time
 
     cache = str(tmp_path / "autotune_cache.json")
     shutil.copy(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                              "paper_2411_15001_amd", "autotune_cache.json"), cache)
-    n = 2048
+    n, steps = 2048, 1000
     u0 = cases.double_rarefaction(n, seed=0)
     ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 2 | 8, bc_x=1, bc_y=1)
     s = Solver(u0, **okw(ocfg))
     s.autotune(cache)
-    s.step(2)
-    G = s.get_state().cpu().numpy()
-    S, _ = oracle.init(ocfg, u0)
-    S, _, _, _ = oracle.run(ocfg, S, 2)
-    assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
-    del G, S
-    s.step(998)
+    s.step(steps)
     d = s.diagnostics()  # before moments(), which clears the counters
+    G = s.get_state().cpu().numpy()
     m = s.moments().cpu().numpy()  # raises on a positivity event
+    s.close()
     assert d["n_bad"] == 0 and d["n_guard"] == 0
     # the new density never left the eq. (29) bounds over the 1000 steps
     assert d["n_lmp"] == 0
     p = 0.4 * (m[3] - 0.5 * (m[1] ** 2 + m[2] ** 2) / m[0])
     assert m[0].min() > 0 and p.min() > 0
-    s.close()
+    del m
+    S, _ = oracle.init(ocfg, u0)
+    t0 = time.time()
+    tot = np.zeros(4, np.int64)
+    for k in range(0, steps, 100):
+        S, _, _, tt = oracle.run(ocfg, S, 100)
+        tot += tt
+        with capsys.disabled():
+            print("  oracle C1: %d / %d steps, %.0f s" % (k + 100, steps, time.time() - t0), flush=True)
+    assert tot[2] == 0 and tot[3] == 0
+    assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
+    assert d["n_limited"] == tot[1]
 
 
 def test_fp32_form_against_oracle():
@@ -298,12 +408,13 @@ def test_fp32_form_against_oracle():
 
 
 def test_fp32_form_1024_against_oracle():
-    """FP32-state form on the blast at 1024^2 (the accuracy size of the
-    8192^2 benchmark), 500 steps, against the FP64 oracle: relative L1 error
-    of the density within the 1e-4 target or, where the PP-limited blast
-    has become sensitive, within three times the oracle's own spread from a
-    one-float32-rounding perturbation of the initial data (+1e-4).  Both
-    numbers are printed."""
+    """The blast at 1024^2 (the accuracy size of the 8192^2 benchmark), 500
+    steps, against the FP64 oracle.  The FP64 form equals the oracle bit for
+    bit after all 500 steps.  The FP32-state form's relative L1 error of the
+    density is held to 1.5 times its recorded value (2.9e-3): the PP-limited
+    blast has become sensitive by then, the oracle itself moving by ~4.9e-3
+    from a one-float32-rounding perturbation of the initial data, so the 1e-4
+    target cannot hold at this size and horizon.  Both numbers are printed."""
     n, steps = 1024, 500
     u0 = cases.blast(n, seed=0)
     ocfg = oracle.Config(nx=n, ny=n, limiters=1 | 8)
@@ -317,12 +428,17 @@ def test_fp32_form_1024_against_oracle():
         return np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum()
 
     floor = l1(Sp, S)
+    s64 = Solver(u0, **okw(ocfg))
+    s64.step(steps)
+    assert np.array_equal(s64.get_state().cpu().numpy(), S)
+    s64.close()
     s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
     s32.step(steps)
     assert s32.diagnostics()["n_bad"] == 0  # read before moments() clears it
     e = l1(s32.moments().cpu().numpy(), S)
     print("fp32 blast 1024^2 rel L1 rho after %d steps %.3e (oracle floor %.3e)" % (steps, e, floor))
-    assert e <= max(1e-4, 3 * floor + 1e-4)
+    assert e <= 1.5 * 2.9e-3
+    assert e <= floor
     s32.close()
 
 
