@@ -290,14 +290,21 @@ def record_traffic(fetch_csv, write_csv, line_path, trace_csv=None):
             for r in csv.DictReader(f):
                 stats[r["Name"]] = (float(r["AverageNs"]), int(r["Calls"]))
     wl = line["config"]["workload"]
-    grid = line["config"]["grid"]
-    cells = grid[0] * grid[1]
-    base = ("blast" if wl.startswith("blast") else "rarefaction") + "%d" % grid[0]
-    if "RLMP" in wl:
-        base += "_rlmp"
+    if wl.startswith("batch"):
+        # the ensemble: one FP32-state form, its launch shape at the top level
+        cells = line["config"]["cells"]
+        base = "batch%d" % line["config"]["instances"]
+        forms = {"fp32": {"launch": line["launch"]}}
+    else:
+        grid = line["config"]["grid"]
+        cells = grid[0] * grid[1]
+        base = ("blast" if wl.startswith("blast") else "rarefaction") + "%d" % grid[0]
+        if "RLMP" in wl:
+            base += "_rlmp"
+        forms = line["forms"]
     sha = kernel_source_digest()
     rec["source_sha256"] = sha
-    for form, v in line["forms"].items():
+    for form, v in forms.items():
         tname = "double" if form == "fp64" else "float"
         pick = lambda rows: [x for k, x in rows if "step_kernel<%s" % tname in k]
         fv, wv = pick(fetch), pick(write)

@@ -412,14 +412,21 @@ def lbm_set_strip_mode(ctx, mode=0):
 def _boundary_ptrs(ctx, inst, side, kind, state):
     import torch
 
-    nx, ny = _inst_shape(ctx, int(inst))
-    n = ny if int(side) in (0, 1) else nx
+    sh = _shapes.get(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx)
+    if sh is None:
+        raise ValueError("unknown or destroyed context")
+    # an instance index out of range goes to the library unchecked, which
+    # rejects it (LBM_EINVAL) before reading any description
+    n = None
+    if 0 <= int(inst) < len(sh):
+        nx, ny = sh[int(inst)]
+        n = ny if int(side) in (0, 1) else nx
     kp = sp = None
     if kind is not None:
         _require_cuda(kind, torch.uint8, n, "kind")
         kp = _ptr(kind)
         if state is not None:
-            _require_cuda(state, torch.float64, 4 * n, "state")
+            _require_cuda(state, torch.float64, None if n is None else 4 * n, "state")
             sp = _ptr(state)
     return kp, sp
 

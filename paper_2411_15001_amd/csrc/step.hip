@@ -106,12 +106,18 @@ __device__ __forceinline__ double theta_rho_lmp(double rs, double D, double kapp
   // the caller takes min(1, .): when the dividend already reaches D (in the
   // direction of its sign) the rounded quotient is >= 1, and 1 stands in for
   // it without the division
-  if (D > 0.0) {
-    const double num = kappa * vmin(nuR - rs, rs - muL);
-    return num >= D ? 1.0 : num / D;
+  const bool pos = D > 0.0;
+  const double num = pos ? kappa * vmin(nuR - rs, rs - muL) : -kappa * vmin(rs - muR, nuL - rs);
+  const bool one = pos ? (num >= D) : (num <= D);
+  double q = 1.0;
+  if (!one) {
+    // an empty volatile statement keeps the division inside the branch, so
+    // that a wave with no limited face skips it instead of evaluating it on
+    // every lane and selecting
+    __asm__ volatile("");
+    q = num / D;
   }
-  const double num = -kappa * vmin(rs - muR, nuL - rs);
-  return num <= D ? 1.0 : num / D;
+  return q;
 }
 
 // Relative slack of the LMP check: the rounding of the update (float64
@@ -121,6 +127,8 @@ constexpr double kLmpTol = sizeof(T) == 8 ? 1e-12 : 2e-6;
 
 // Margin of the division-free test below: c = 1 + 2^-30.
 constexpr double kFastMargin = 1.0 + 0x1p-30;
+// Margin of the square-root-free test in front of it: m = 1 - 2^-26.
+constexpr double kPreMargin = 1.0 - 0x1p-26;
 
 // theta = min(1, selected theta^rho, theta^p) of one face (Section 3.2).  A
 // face state outside the admissible set takes the first-order value 0.
@@ -133,6 +141,14 @@ constexpr double kFastMargin = 1.0 + 0x1p-30;
 // bring a value above 1 + 2^-32 below 1).  In that case min(1, ...) over those
 // two limiters is exactly 1 and the four divisions are skipped; every other
 // lane evaluates the formulas in full, so the result is bit-identical.
+//
+// The square root behind N is skipped as well where a test without it
+// already implies the one above: with X = fl(kappa (-2 g0)), a = fl(X m) and
+// t = fl(a - |g1|) in [2^-500, 2^500), disc <= fl(fl(t t) m) gives
+// fl(sqrt(disc)) <= t sqrt(m) (1 + u)^2 <= (a - |g1|) sqrt(m) (1 + u)^3 <
+// a - |g1|, so |g1| + sqrt < a <= X m (1 + u) and fl(N c) <= X m c (1 + u)^3
+// < X (m c < 1 - 2^-27).  The range of t keeps every product normal and
+// finite; a NaN or an infinity fails the test and takes the full path.
 //
 // LIMS != 0 fixes the limiter set at compile time (the launcher selects such
 // a kernel only for the second-order scheme without sponge layers and with
@@ -170,17 +186,24 @@ __device__ __forceinline__ double face_theta(const Scheme& s, const C us[4], con
     const double g2 = Dm1 * Dm1 + Dm2 * Dm2 - 2.0 * D * DE;
     double disc = g1 * g1 - 4.0 * g0 * g2;
     disc = vmax(0.0, disc);
-    const double N = fabs(g1) + sqrt(disc);
     const double Dn = -2.0 * g0;
-    const bool fast_p = fast_rho && N * kFastMargin <= kappa * Dn;
-    if (!fast_p) {
-      // theta^p = max(0, kappa / r - eps) with r the larger of |D| / rho* and
-      // (|g1| + sqrt(disc)) / (-2 g0) (Section 3.4), reusing g0, g1, disc, N
-      const double e1 = fabs(D) / r0;
-      const double e2 = N / Dn;
-      const double r = vmax(e1, e2);
-      const double tp = (r == 0.0) ? kHuge : vmax(0.0, kappa / r - s.eps);
-      t = vmin(t, tp);
+    const double X = kappa * Dn;
+    const double tq = X * kPreMargin - fabs(g1);
+    const bool pre = fast_rho && tq >= 0x1p-500 && tq < 0x1p500 && disc <= (tq * tq) * kPreMargin;
+    if (!pre) {
+      __asm__ volatile("");  // keeps the square root inside the branch
+      const double N = fabs(g1) + sqrt(disc);
+      const bool fast_p = fast_rho && N * kFastMargin <= X;
+      if (!fast_p) {
+        // theta^p = max(0, kappa / r - eps) with r the larger of |D| / rho*
+        // and (|g1| + sqrt(disc)) / (-2 g0) (Section 3.4), reusing g0, g1,
+        // disc, N
+        const double e1 = fabs(D) / r0;
+        const double e2 = N / Dn;
+        const double r = vmax(e1, e2);
+        const double tp = (r == 0.0) ? kHuge : vmax(0.0, kappa / r - s.eps);
+        t = vmin(t, tp);
+      }
     }
   }
   return t;
@@ -1073,8 +1096,8 @@ typedef __attribute__((address_space(3))) void lds_void;
 // from 16 lanes.
 // Arithmetic, evaluation order and results are those of march_lmp; only where
 // the loaded values wait differs.  Used for single instances whose width is a
-// multiple of 64 (every strip full) with the limiter set fixed at compile
-// time.  The loads into LDS are not tracked by the compiler's wait counters:
+// multiple of 64 (every strip full) and that have no boundary descriptions.
+// The loads into LDS are not tracked by the compiler's wait counters:
 // the march waits on the vector-memory counter itself (see the loop head).
 template <class T, class C, int LIMS, bool TH>
 __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in, Slots* sl, int xs,
@@ -1089,6 +1112,7 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
 
   const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
+  const bool sponge = LIMS == 0 && sc.sponge > 0;
 
   if (xs == 0 && ys == 0 && lane == 0) {
     sl->lam[(A.slot + 2) % 3] = 0ull;
@@ -1260,9 +1284,14 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
     const C muE = from_right_or(mu1, hmu);
     const C nuE = from_right_or(nu1, hnu);
     int gx, gy, gw;
-    const double thx = face_theta<LIMS>(sc, pusx, pdF, K.kappa, mu1, nu1, muE, nuE, gx);
-    const double thy = face_theta<LIMS>(sc, pusy, pdG, K.kappa, pmu, pnu, mu1, nu1, gy);
-    const double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, hmu, hnu, mu1, nu1, gw);
+    double thx = face_theta<LIMS>(sc, pusx, pdF, K.kappa, mu1, nu1, muE, nuE, gx);
+    double thy = face_theta<LIMS>(sc, pusy, pdG, K.kappa, pmu, pnu, mu1, nu1, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, hmu, hnu, mu1, nu1, gw);
+    if (sponge) {
+      if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi + 1, L - 1, nx, ny)) thx = 0.0;
+      if (in_sponge(sc, gi, L - 2, nx, ny) || in_sponge(sc, gi, L - 1, nx, ny)) thy = 0.0;
+      if (in_sponge(sc, x0 - 1, L - 1, nx, ny) || in_sponge(sc, x0, L - 1, nx, ny)) th_edge = 0.0;
+    }
     const bool row1 = L - 1 >= y0 && L - 1 < y1;
     const bool row2 = L - 2 >= y0 && L - 2 < y1;
     if (row1 && !last) {
@@ -1277,7 +1306,7 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
       n_guard += gw;
       n_lim += (th_edge < 1.0);
     }
-    if (TH) {
+    if (TH || (LIMS == 0 && A.theta_x)) {
       if (row1 && first) A.theta_x[(long long)(L - 1) * (nx + 1) + x0] = th_edge;
       if (row1) A.theta_x[(long long)(L - 1) * (nx + 1) + gi + 1] = thx;
       if ((row1 || row2) && L - 1 >= 0 && L - 1 <= ny) A.theta_y[(long long)(L - 1) * nx + gi] = thy;
@@ -1834,7 +1863,9 @@ __global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int slot) {
 // kernels, and a grid with boundary descriptions the general kernels that
 // read them.
 // The LDS-staged bounds-limited march needs every strip full (width a
-// multiple of 64) and a single instance; its LDS (three rows per wave) is
+// multiple of 64), a single instance and no boundary descriptions; it runs
+// for every limiter set with density bounds (fixed at compile time for the
+// LMP and RLMP sets with PP and pressure).  Its LDS (three rows per wave) is
 // dynamic, above the default limit in float64.
 template <class T, int WPE, int LIMS, bool TH>
 static void launch_dma(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s) {
@@ -1857,11 +1888,20 @@ template <class T, bool LMP, int WPE>
 static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
   if constexpr (LMP) {
-    if (lims == kFixed && dma_ok(a)) {
-      if (a.theta_x)
+    if (dma_ok(a)) {
+      // PP + LMP + pressure and PP + RLMP + pressure with the set fixed;
+      // every other set, and sponge layers, with the set read at run time
+      constexpr int kRelaxed = 1 | 4 | 8;
+      if (lims == kFixed && a.theta_x)
         launch_dma<T, WPE, kFixed, true>(a, grid, block, s);
-      else
+      else if (lims == kFixed)
         launch_dma<T, WPE, kFixed, false>(a, grid, block, s);
+      else if (lims == kRelaxed && a.theta_x)
+        launch_dma<T, WPE, kRelaxed, true>(a, grid, block, s);
+      else if (lims == kRelaxed)
+        launch_dma<T, WPE, kRelaxed, false>(a, grid, block, s);
+      else
+        launch_dma<T, WPE, 0, false>(a, grid, block, s);
       return;
     }
   }

@@ -192,50 +192,64 @@ def test_fixed_limiter_kernels(prec, lims):
 # (PP + LMP + pressure, single instance); heights, strip heights, grids and
 # boundaries vary the ring's prologue and tail
 LDS_CASES = [
-    # nx, ny, bc_x, bc_y, strip rows, waves, groups per CU, precision
-    (64, 1, 1, 1, 4, 1, 0, B.LBM_FP64),
-    (64, 3, 0, 0, 4, 4, 0, B.LBM_FP64),
-    (128, 70, 1, 1, 16, 4, 0, B.LBM_FP64),
-    (192, 37, 0, 1, 64, 2, 0, B.LBM_FP64),
-    (256, 130, 1, 0, 8, 4, 1, B.LBM_FP64),
-    (128, 64, 1, 1, 4096, 1, 0, B.LBM_FP64),
-    (64, 5, 1, 1, 4, 4, 0, B.LBM_FP32_STATE),
-    (192, 99, 1, 1, 32, 4, 0, B.LBM_FP32_STATE),
-    (256, 64, 0, 0, 16, 2, 2, B.LBM_FP32_STATE),
+    # nx, ny, bc_x, bc_y, strip rows, waves, groups per CU, precision, limiters, sponge
+    (64, 1, 1, 1, 4, 1, 0, B.LBM_FP64, 1 | 2 | 8, 0),
+    (64, 3, 0, 0, 4, 4, 0, B.LBM_FP64, 1 | 2 | 8, 0),
+    (128, 70, 1, 1, 16, 4, 0, B.LBM_FP64, 1 | 2 | 8, 0),
+    (192, 37, 0, 1, 64, 2, 0, B.LBM_FP64, 1 | 2 | 8, 0),
+    (256, 130, 1, 0, 8, 4, 1, B.LBM_FP64, 1 | 2 | 8, 0),
+    (128, 64, 1, 1, 4096, 1, 0, B.LBM_FP64, 1 | 2 | 8, 0),
+    (64, 5, 1, 1, 4, 4, 0, B.LBM_FP32_STATE, 1 | 2 | 8, 0),
+    (192, 99, 1, 1, 32, 4, 0, B.LBM_FP32_STATE, 1 | 2 | 8, 0),
+    (256, 64, 0, 0, 16, 2, 2, B.LBM_FP32_STATE, 1 | 2 | 8, 0),
+    # PP + RLMP + pressure (a set fixed at compile time)
+    (128, 70, 1, 1, 16, 4, 0, B.LBM_FP64, 1 | 4 | 8, 0),
+    (192, 40, 0, 0, 8, 2, 0, B.LBM_FP32_STATE, 1 | 4 | 8, 0),
+    # sets read at run time, sponge layers
+    (128, 66, 1, 1, 8, 4, 0, B.LBM_FP64, 2 | 8, 0),
+    (192, 50, 1, 1, 16, 4, 0, B.LBM_FP64, 1 | 2 | 4 | 8, 3),
+    (128, 41, 1, 0, 4, 1, 0, B.LBM_FP64, 2, 5),
+    (256, 33, 0, 1, 8, 4, 0, B.LBM_FP64, 4 | 8, 2),
+    (256, 33, 0, 1, 8, 4, 0, B.LBM_FP32_STATE, 4 | 8, 0),
 ]
 
 
-@pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: "%dx%d-bc%d%d-h%d-w%d-g%d-p%d" % c)
+@pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: "%dx%d-bc%d%d-h%d-w%d-g%d-p%d-l%d-s%d" % c)
 def test_lds_staged_lmp_march(case, gpu):
     """The LDS-staged bounds-limited march (rows brought two ahead by direct
     loads into LDS) against the register-staged one: the same states,
-    counters and face factors bit for bit, and in float64 the oracle's."""
-    nx, ny, bx, by, rows, waves, gpc, prec = case
+    counters and face factors bit for bit, and in float64 the oracle's; for
+    the limiter sets fixed at compile time and for those read at run time,
+    with and without sponge layers (ensembles have none: those cases are
+    compared with the oracle only)."""
+    nx, ny, bx, by, rows, waves, gpc, prec, lims, sponge = case
+    assert prec == B.LBM_FP64 or not sponge
     u0 = np.ascontiguousarray(cases.riemann4(max(nx, ny), seed=nx + ny)[:, :ny, :nx])
-    ocfg = oracle.Config(nx=nx, ny=ny, limiters=1 | 2 | 8, a_beta=1.1, bc_x=bx, bc_y=by)
+    ocfg = oracle.Config(nx=nx, ny=ny, limiters=lims, a_beta=1.1, bc_x=bx, bc_y=by, sponge=sponge)
     a = Solver(u0, precision=prec, **okw(ocfg))
     a.set_launch(rows, waves, groups_per_cu=gpc)
-    # the register-staged march: an ensemble (two copies) takes it
-    kw = okw(ocfg)
-    kw.pop("dx")
-    b = BatchSolver([u0, u0], precision=prec, dx=[1.0 / nx] * 2, **kw)
     steps = 12
     for k in range(steps):
         if k % 4 == 3:
             tx, ty = a.step_theta()
         else:
             a.step(1)
-    b.step(steps)
     G = a.get_state().cpu().numpy()
     da = a.diagnostics()
     ma = a.moments().cpu().numpy()
     a.close()
-    db = b.diagnostics(0)  # before moments(), which clears the counters
-    for i in range(2):
-        assert np.array_equal(ma, b.moments(i).cpu().numpy()), i
-    for k in ("n_guard", "n_limited", "n_bad", "n_lmp", "lam"):
-        assert da[k] == db[k], (k, da[k], db[k])
-    b.close()
+    if not sponge:
+        # the register-staged march: an ensemble (two copies) takes it
+        kw = okw(ocfg)
+        kw.pop("dx")
+        b = BatchSolver([u0, u0], precision=prec, dx=[1.0 / nx] * 2, **kw)
+        b.step(steps)
+        db = b.diagnostics(0)  # before moments(), which clears the counters
+        for i in range(2):
+            assert np.array_equal(ma, b.moments(i).cpu().numpy()), i
+        for k in ("n_guard", "n_limited", "n_bad", "n_lmp", "lam"):
+            assert da[k] == db[k], (k, da[k], db[k])
+        b.close()
     if prec == B.LBM_FP64:
         S, _ = oracle.init(ocfg, u0)
         S, _, _, tot = oracle.run(ocfg, S, steps - 1)
