@@ -1187,14 +1187,29 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
   issue(y0 - 1, 1);
   int b = 0;
   for (int L = y0 - 2; L <= y1 + 1; ++L) {
-    // row L has arrived when at most the newest row's loads (issued at the
-    // end of the previous iteration, after every store) are outstanding; in
-    // the last iteration nothing newer was issued
-    if (L + 1 <= y1 + 1)
+    // Row L's loads were issued at the top of iteration L - 2.  The vector
+    // memory counter drains in issue order, so row L has arrived when no more
+    // operations are outstanding than were issued after it: the 20 stores of
+    // iteration L - 2, row L + 1's loads and the 20 stores of iteration L - 1.
+    // That count is exact where both iterations stored both of their rows
+    // (every store is then issued, and the face-factor stores of the TH
+    // kernels are absent); elsewhere the march waits for row L + 1 too
+    // (vmcnt(kRowOps)), or for everything where row L + 1 was not requested.
+    // Waiting for fewer outstanding operations than the exact count is
+    // always safe; the exact count lets the stores of the last two
+    // iterations drain while the next row is computed.
+    if (!TH && L - 4 >= y0 && L <= y1)
+      __builtin_amdgcn_s_waitcnt(sizeof(T) == 8 ? 0xCF73 : 0x8F7E);  // vmcnt(40 + kRowOps)
+    else if (L + 1 <= y1 + 1)
       __builtin_amdgcn_s_waitcnt(sizeof(T) == 8 ? 0x0F7B : 0x0F76);  // vmcnt(kRowOps)
     else
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    static_assert(kRowOps == (sizeof(T) == 8 ? 11 : 6), "wait count of the loop head");
+    static_assert(kRowOps == (sizeof(T) == 8 ? 11 : 6), "wait counts of the loop head");
+    // row L + 2 goes into the buffer of row L - 1, whose values were read
+    // into registers in the previous iteration
+    __builtin_amdgcn_sched_barrier(0);
+    if (L + 2 <= y1 + 1) issue(L + 2, b == 0 ? 2 : b - 1);
+    __builtin_amdgcn_sched_barrier(0);
     const unsigned char* rb = ring + b * dma_row_bytes<T>();
     const T* rowv = (const T*)rb;
     const T* hrow = (const T*)(rb + 20 * 64 * (int)sizeof(T));
@@ -1384,12 +1399,6 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
 #pragma unroll
       for (int k = 0; k < 4; ++k) puk[k][c] = uk[k][c];
     }
-    // the next loads go into the buffer of row L - 1, consumed a full
-    // iteration ago, after this iteration's stores (so that the loop head's
-    // count of newer operations is exactly one row's loads)
-    __builtin_amdgcn_sched_barrier(0);
-    if (L + 2 <= y1 + 1) issue(L + 2, b == 0 ? 2 : b - 1);
-    __builtin_amdgcn_sched_barrier(0);
     b = b == 2 ? 0 : b + 1;
   }
 
