@@ -89,16 +89,21 @@ def parse():
 
 def calibration_copy(gib):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give the
-    scale between those counters and bytes moved."""
+    scale between those counters and bytes moved.  The copy is torch's
+    elementwise negation (one dispatch per launch, each element read once and
+    written once), whose kernel name (neg_kernel) no other dispatch of this
+    script shares; the runtime's copy kernel serves every other copy and
+    splits large ones over several dispatches."""
     import torch
 
     n = int(gib * (1 << 30)) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
-    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}
+    return {"kernel": "neg_kernel", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+            "launches": 3}
 
 
 def time_form(form, u0t, n, steps, warmup, autotune, total_steps=0):
@@ -243,15 +248,15 @@ def _oracle_blast_rate(n, steps):
 
 
 def _counter_rows(csv_path, counter):
-    """(kernel name, value) of every dispatch of one counter in a rocprofv3
-    counter-collection CSV."""
+    """(kernel name, value, grid size) of every dispatch of one counter in a
+    rocprofv3 counter-collection CSV, in dispatch order."""
     import csv
 
     out = []
     with open(csv_path) as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] == counter:
-                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+                out.append((r["Kernel_Name"], float(r["Counter_Value"]), int(r["Grid_Size"])))
     return out
 
 
@@ -277,18 +282,43 @@ def record_traffic(fetch_csv, write_csv, line_path, trace_csv=None):
     except OSError:
         rec = {}
     if calib:
-        cf = [v for k, v in fetch if "copyBuffer" in k]
-        cw = [v for k, v in write if "copyBuffer" in k]
-        copy_kib = calib["bytes_read"] / calib["launches"] / 1024.0
-        rec["calibration"] = {"fetch_factor": copy_kib / (sum(cf) / len(cf)),
-                              "write_factor": copy_kib / (sum(cw) / len(cw)),
+        cf = [v for k, v, _ in fetch if calib["kernel"] in k]
+        cw = [v for k, v, _ in write if calib["kernel"] in k]
+        if len(cf) != calib["launches"] or len(cw) != calib["launches"]:
+            raise SystemExit("calibration: expected %d dispatches of %s, found %d / %d"
+                             % (calib["launches"], calib["kernel"], len(cf), len(cw)))
+        rd_kib = calib["bytes_read_per_launch"] / 1024.0
+        wr_kib = calib["bytes_written_per_launch"] / 1024.0
+        rec["calibration"] = {"kernel": calib["kernel"], "bytes_per_launch": calib["bytes_read_per_launch"],
+                              "fetch_factor": rd_kib / (sum(cf) / len(cf)),
+                              "write_factor": wr_kib / (sum(cw) / len(cw)),
                               "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
     cal = rec["calibration"]
+    # the timed launches of each step kernel are its last dispatches in the
+    # counter run: they are told apart from its other dispatches (untimed
+    # steps at another launch shape before the autotuner's pick, the FP32
+    # form's error run at 1024^2) by the grid size of the last one
+    grids = {}
+    for k, _, g in fetch:
+        grids[k] = {g}
     stats = {}
     if trace_csv:
         with open(trace_csv) as f:
-            for r in csv.DictReader(f):
-                stats[r["Name"]] = (float(r["AverageNs"]), int(r["Calls"]))
+            rows = list(csv.DictReader(f))
+        if rows and "Grid_Size_X" in rows[0]:
+            # per-dispatch kernel trace: the average over the dispatches whose
+            # kernel and grid size the counter run shows
+            acc = {}
+            for r in rows:
+                g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                if g in grids.get(r["Kernel_Name"], ()):
+                    a = acc.setdefault(r["Kernel_Name"], [0, 0])
+                    a[0] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                    a[1] += 1
+            stats = {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+        else:
+            # --stats summary: every dispatch of the kernel
+            stats = {r["Name"]: (float(r["AverageNs"]), int(r["Calls"])) for r in rows}
     wl = line["config"]["workload"]
     if wl.startswith("batch"):
         # the ensemble: one FP32-state form, its launch shape at the top level
@@ -306,7 +336,7 @@ def record_traffic(fetch_csv, write_csv, line_path, trace_csv=None):
     rec["source_sha256"] = sha
     for form, v in forms.items():
         tname = "double" if form == "fp64" else "float"
-        pick = lambda rows: [x for k, x in rows if "step_kernel<%s" % tname in k]
+        pick = lambda rows: [x for k, x, g in rows if "step_kernel<%s" % tname in k and g in grids[k]]
         fv, wv = pick(fetch), pick(write)
         if not fv or not wv:
             continue

@@ -26,17 +26,19 @@ def test_source_digest_ignores_comments_only():
     assert len(d) == 64 and d == bench.kernel_source_digest()
 
 
-def _algorithmic():
-    """Algorithmic HBM bytes per launch: 20 state values read and written per
-    cell, 4 bytes each in the float32-state form, 8 in float64."""
+def _algorithmic(key):
+    """Algorithmic HBM bytes per launch of a recorded workload/form key: 20
+    state values read and written per cell, 4 bytes each in the
+    float32-state form, 8 in float64."""
+    import re
+
     from paper_2411_15001_amd import cases
 
-    batch_cells = sum(int(n) ** 2 for n in cases.batch_sides(256, seed=0))
-    return {"blast8192_fp32": 8192 ** 2 * 160, "blast8192_fp64": 8192 ** 2 * 320,
-            "rarefaction2048_fp64": 2048 ** 2 * 320, "batch256_fp32": batch_cells * 160}
-
-
-ALGORITHMIC = _algorithmic()
+    bpc = 160 if key.endswith("_fp32") else 320
+    if key.startswith("batch256"):
+        return sum(int(n) ** 2 for n in cases.batch_sides(256, seed=0)) * bpc
+    m = re.match(r"(blast|rarefaction)(\d+)_", key)
+    return int(m.group(2)) ** 2 * bpc
 
 
 def _record():
@@ -58,7 +60,8 @@ def test_traffic_lookup_matches_launch_shape():
         assert got == entry["bytes_per_launch"], key
         # the measured bytes lie at most 15% above the algorithmic ones (the
         # re-read halo rows and columns) and not below them
-        ratio = got / ALGORITHMIC[key]
+        assert entry["algorithmic_bytes"] == _algorithmic(key), key
+        ratio = got / _algorithmic(key)
         assert 1.0 <= ratio < 1.15, (key, ratio)
         # another strip height has other halo re-reads: no figure
         other = [launch[0] * 2] + list(launch[1:])
