@@ -35,6 +35,8 @@
 
 #include <math.h>
 
+#include <atomic>
+
 #include "vlbm_internal.h"
 
 namespace vlbm {
@@ -1879,9 +1881,19 @@ __global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int slot) {
 template <class T, int WPE, int LIMS, bool TH>
 static void launch_dma(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s) {
   const auto k = step_kernel<T, T, true, WPE, LIMS, TH, false, true>;
-  static const hipError_t attr =
-      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, dma_lds_bytes<T>(4));
-  (void)attr;
+  // the limit is a property of the function on each device: raise it on the
+  // first launch on every device (a failure leaves the error for the
+  // launcher's hipGetLastError, and the launch itself then fails too)
+  static std::atomic<unsigned long long> raised{0};
+  int dev = -1;
+  const bool known = hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64;
+  const unsigned long long bit = known ? 1ull << dev : 0ull;
+  if (!known || !(raised.load(std::memory_order_acquire) & bit)) {
+    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, dma_lds_bytes<T>(4)) ==
+            hipSuccess &&
+        known)
+      raised.fetch_or(bit, std::memory_order_acq_rel);
+  }
   hipLaunchKernelGGL(k, grid, block, (unsigned)dma_lds_bytes<T>((int)block.x / 64), s, a);
 }
 
