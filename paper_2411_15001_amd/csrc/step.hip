@@ -1077,9 +1077,9 @@ __device__ __forceinline__ void march_lmp(const StepArgs& A, const Inst& in, Slo
 
 // ------------------------------------------ bounds-limited march, LDS-staged
 
-// Rows of the state in flight for the LDS-staged march: the row being
-// consumed and the two behind it.  Each row occupies 20 planes x 64 columns
-// of T followed by the 16 halo loads of 16 bytes each.
+// Row buffers per wave of the LDS-staged march: the row being consumed and
+// the two requested after it.  Each row occupies 20 planes x 64 columns of T
+// followed by the 16 halo loads of 16 bytes each.
 constexpr int kDmaRing = 3;
 constexpr int kDmaHaloBytes = 16 * 16;
 template <class T>

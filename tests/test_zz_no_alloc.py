@@ -46,6 +46,9 @@ CASES = [
     ((130, 70), (33, 17), dict(limiters=1 | 2 | 8, bc_x=1, bc_y=1, sponge=3), 3),
     ((200, 136), (72, 40), dict(precision=B.LBM_FP32_STATE, limiters=1 | 8, a_beta=1.1, bc_x=1, bc_y=1), 6),
     ((200, 136), (72, 40), dict(precision=B.LBM_FP32_STATE, limiters=1 | 2 | 8, bc_x=1, bc_y=1), 6),
+    # widths that are multiples of 64: the LDS-staged bounds-limited march
+    ((256, 96), (128, 40), dict(limiters=1 | 2 | 8, a_beta=1.1, bc_x=1, bc_y=1), 5),
+    ((192, 64), (64, 70), dict(precision=B.LBM_FP32_STATE, limiters=1 | 4 | 8, bc_x=1, bc_y=0), 5),
 ]
 
 
