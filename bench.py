@@ -358,6 +358,16 @@ def record_traffic(fetch_csv, write_csv, line_path, trace_csv=None):
     return rec
 
 
+def with_speedup(cb, gpu_glups):
+    """The GPU's rate over the oracle's (all host cores, and one core where
+    timed) for each form in gpu_glups ({form: GLUPS}); a ratio of rates, not a
+    measure of the kernel's quality (the roofline fraction is that)."""
+    cb["gpu_over_cpu"] = {f: v / cb["value"] for f, v in gpu_glups.items()}
+    if "single_thread" in cb:
+        cb["gpu_over_cpu_one_core"] = {f: v / cb["single_thread"]["value"] for f, v in gpu_glups.items()}
+    return cb
+
+
 def cpu_baseline(n, steps, workload_steps=500):
     """The oracle timed on the blast workload's own grid (n x n): `steps`
     steps with OpenMP over rows on every host core the process may use, and
@@ -560,7 +570,8 @@ def bench_rarefaction(a):
           {"workload": "near-vacuum double rarefaction %dx%d, outflow, PP + %s + pressure, "
                        "a = 4 lambda, %s form" % (n, n, a.bounds.upper(), forms_req[0]), "grid": [n, n]},
           H["roofline"], status=H["status"], launch=H["launch"], forms=forms,
-          **({} if a.no_cpu else {"cpu_baseline": cpu_rarefaction(min(n, 2048))}))
+          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_rarefaction(min(n, 2048)),
+                                                               {f: v["value"] for f, v in forms.items()})}))
 
 
 def bench_batch(a):
@@ -619,7 +630,8 @@ def bench_batch(a):
           {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("batch256_fp32", launch)}, status=int(st),
           launch=list(launch), per_class=per_class,
-          **({} if a.no_cpu else {"cpu_baseline": cpu_batch(sides, u0s)}))
+          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_batch(sides, u0s),
+                                                               {"fp32": cells / (avg * 1e-3) / 1e9})}))
 
 
 def bench_adjoint(a):
@@ -669,7 +681,8 @@ def bench_adjoint(a):
           roofline_scope="whole gradient: algorithmic bytes of the forward (320 B), recompute "
                          "(336 B: state + theta) and adjoint (496 B: U, Ubar in, theta, Ubar out) "
                          "cell-steps over the gradient time; state copies excluded",
-          **({} if a.no_cpu else {"cpu_baseline": cpu_adjoint(u0, a_fixed)}))
+          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_adjoint(u0, a_fixed),
+                                                               {"fp64": cell_steps / (ms * 1e-3) / 1e9})}))
 
 
 def main():
@@ -756,7 +769,8 @@ def main():
     if not a.no_cpu:
         if "fp32" in forms and not a.no_oracle_error:
             out["fp32_error_vs_oracle"] = fp32_error_vs_oracle()
-        out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.cpu_steps)
+        out["cpu_baseline"] = with_speedup(cpu_baseline(a.cpu_n, a.cpu_steps),
+                                           {f: v["value"] for f, v in forms.items()})
     print(json.dumps(out))
 
 
