@@ -65,6 +65,15 @@ def parse():
                     help="comma-separated forms (default fp32,fp64 for blast, fp64 for rarefaction)")
     ap.add_argument("--bounds", default="lmp", choices=["lmp", "rlmp"],
                     help="rarefaction workload: the density-bounds limiter")
+    ap.add_argument("--alpha", type=float, default=0.5,
+                    help="rarefaction workload: rest weight alpha of the D2Q5 model (Prop. 3)")
+    ap.add_argument("--beta", type=float, default=1.0,
+                    help="rarefaction workload: speed factor beta of a = 2 beta lambda / (1 - alpha)")
+    ap.add_argument("--sponge", type=int, default=0,
+                    help="rarefaction workload: width of the theta = 0 layer at the outflow walls")
+    ap.add_argument("--blend", default="face", choices=["face", "cell"],
+                    help="rarefaction workload: the face blending (the method) or the per-cell blending "
+                         "of Section 3.1 (an ablation)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=8192)
@@ -531,10 +540,16 @@ def bench_rarefaction(a):
     bound = B.LBM_RHO_RLMP if a.bounds == "rlmp" else B.LBM_RHO_LMP
     lims = B.LBM_RHO_PP | bound | B.LBM_PRESSURE
     u0t = torch.from_numpy(cases.double_rarefaction(n, seed=0)).cuda()
+    # a variant of the scheme (its own kernels or parameters): no recorded
+    # counters apply
+    variant = (a.alpha, a.beta, a.sponge, a.blend) != (0.5, 1.0, 0, "face")
+    vdesc = "" if not variant else ", alpha %g, beta %g, sponge %d, %s blending" % (a.alpha, a.beta, a.sponge, a.blend)
     forms = {}
     for form in forms_req:
         prec = B.LBM_FP32_STATE if form == "fp32" else B.LBM_FP64
-        s = Solver(u0t, precision=prec, limiters=lims, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW)
+        s = Solver(u0t, precision=prec, limiters=lims, bc_x=B.LBM_BC_OUTFLOW, bc_y=B.LBM_BC_OUTFLOW,
+                   alpha=a.alpha, a_beta=a.beta, sponge=a.sponge,
+                   blend=B.LBM_BLEND_CELL if a.blend == "cell" else B.LBM_BLEND_FACE)
         if not a.no_autotune:
             # tune on a developed flow (the limiters' slow paths are rare in
             # the first steps), then restart from the initial state
@@ -560,7 +575,7 @@ def bench_rarefaction(a):
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS,
                          "traffic": traffic_for("rarefaction%d_%s%s" % (n, "" if a.bounds == "lmp" else "rlmp_", form),
-                                                launch)}}
+                                                launch) if not variant else None}}
         print("# %s: %.3f GLUPS, %.4f ms/step, %.1f%% of HBM peak" % (
             form, forms[form]["value"], avg, 100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)
     del u0t
@@ -568,7 +583,8 @@ def bench_rarefaction(a):
     _line(METRIC, H["value"], "GLUPS", a.steps, a.warmup, H["ms_per_step"],
           "f32 (theta solve and CFL reduce f64)" if forms_req[0] == "fp32" else "f64",
           {"workload": "near-vacuum double rarefaction %dx%d, outflow, PP + %s + pressure, "
-                       "a = 4 lambda, %s form" % (n, n, a.bounds.upper(), forms_req[0]), "grid": [n, n]},
+                       "a = %g lambda, %s form%s" % (n, n, a.bounds.upper(), 2 * a.beta / (1 - a.alpha),
+                                                     forms_req[0], vdesc), "grid": [n, n]},
           H["roofline"], status=H["status"], launch=H["launch"], forms=forms,
           **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_rarefaction(min(n, 2048)),
                                                                {f: v["value"] for f, v in forms.items()})}))
