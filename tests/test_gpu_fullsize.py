@@ -97,3 +97,44 @@ def test_c3_batch_full_size(cache):
     S, _, _, _ = oracle.run(ocfg, S, 5)
     assert np.array_equal(bs.moments(i).cpu().numpy(), S[0:4])
     bs.close()
+
+
+@pytest.mark.parametrize("bound", ["LMP", "RLMP"])
+def test_rarefaction_bounds_full_size(bound, cache):
+    """8192^2 near-vacuum double rarefaction (outflow, a = 4 lambda^n) with
+    PP + LMP + pressure or PP + RLMP + pressure, in the launch shapes bench.py
+    times (the LDS-staged march): the FP64 form equals the oracle bit for bit
+    after two steps over the whole 20-plane state, with the same lambda, time
+    and counters; the FP32 form stays within 1e-6 relative L1 of the oracle's
+    density and keeps every density inside its bounds."""
+    import torch
+
+    from paper_2411_15001_amd.solver import Solver
+
+    n = 8192
+    u0 = cases.double_rarefaction(n, seed=0)
+    lims = oracle.RHO_PP | (oracle.RHO_LMP if bound == "LMP" else oracle.RHO_RLMP) | oracle.PRESSURE
+    ocfg = oracle.Config(nx=n, ny=n, limiters=lims, bc_x=1, bc_y=1)
+    res = {}
+    for prec in (B.LBM_FP64, B.LBM_FP32_STATE):
+        s = Solver(u0, precision=prec, **okw(ocfg))
+        s.autotune(cache)
+        s.step(2)
+        d = s.diagnostics()
+        res[prec] = (s.get_state().cpu().numpy() if prec == B.LBM_FP64 else s.moments()[0].cpu().numpy(), d)
+        s.close()
+        torch.cuda.empty_cache()
+    S, _ = oracle.init(ocfg, u0)
+    del u0
+    S, t, info, tot = oracle.run(ocfg, S, 2)
+    G, d = res[B.LBM_FP64]
+    assert np.array_equal(G, S)
+    assert d["lam"] == info.lambda_new and d["t"] == t
+    assert [d["n_guard"], d["n_limited"], d["n_bad"], d["n_lmp"]] == list(tot)
+    del G
+    rho32, d32 = res[B.LBM_FP32_STATE]
+    err = float(np.abs(rho32 - S[0]).sum() / np.abs(S[0]).sum())
+    assert err <= 1e-6, err
+    assert d32["n_bad"] == 0 and d32["n_guard"] == 0
+    if bound == "LMP":
+        assert d32["n_lmp"] == 0
