@@ -157,6 +157,12 @@ struct lbm_ctx {
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
   int n_cu = 256;       // compute units of the context's device
   bool detached = false;  // the current state lives in a caller buffer (lbm_step_between)
+  // the context's own state buffers hold the blocked layout (single
+  // instance, nx a multiple of 64, face blending, no boundary descriptions):
+  // a strip row of the state is one contiguous range for the LDS-staged
+  // marches.  Caller buffers (lbm_get_state, lbm_set_state,
+  // lbm_step_between, the adjoint) are planar; the library converts.
+  int blocked = 0;
   // boundary descriptions per instance (caller-owned device arrays; copied
   // to the workspace table for ensembles); per instance and side: any
   // Dirichlet cell
@@ -310,6 +316,8 @@ vlbm::StepArgs make_args(const lbm_ctx* c, const void* src, void* dst, int slot)
   else if (!c->bnd.empty())
     a.bnd1 = c->bnd[0];
   a.bnd = c->has_bnd ? 1 : 0;
+  // a step of the context's own state, from its current buffer to the other
+  a.blocked = (c->blocked && src == c->cur() && dst == c->other()) ? 1 : 0;
   return a;
 }
 
@@ -394,6 +402,7 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   c->p = *p;
   c->sc = make_scheme(p);
   c->n_inst = n;
+  c->blocked = (n == 1 && nx[0] % 64 == 0 && p->blend == LBM_BLEND_FACE) ? 1 : 0;
   c->stream = (hipStream_t)stream;
   c->lay = layout(p, n, nx, ny);
   c->ws = (char*)ws;
@@ -433,7 +442,7 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
                                        (long long)(sizeof(Slots) * n / 4), c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_init(c->sc, c->insts.data(), n, c->insts_dev, c->plane, u0, c->cur(),
-                          c->slots, p->precision, c->stream);
+                          c->slots, p->precision, c->blocked, c->stream);
   if (e != hipSuccess) {
     std::string m = std::string("init launch: ") + hipGetErrorString(e);
     delete c;
@@ -587,7 +596,7 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* out) {
   if (inst < 0 || inst >= c->n_inst) return fail(c, LBM_EINVAL, "instance index out of range");
   if (!out) return fail(c, LBM_EINVAL, "output must be a device pointer");
   if (lbm_status st0 = require_attached(c)) return st0;
-  hipError_t e = vlbm::launch_moments(c->insts[inst], c->plane, c->cur(), out, c->p.precision,
+  hipError_t e = vlbm::launch_moments(c->insts[inst], c->plane, c->cur(), out, c->p.precision, c->blocked,
                                       c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "moments launch");
   std::vector<Slots> h;
@@ -641,7 +650,8 @@ lbm_status lbm_diagnostics(lbm_ctx* c, int32_t inst, lbm_diag* d) {
   std::vector<double> part;
   if (!c->detached) {
     double* dp = (double*)(c->ws + c->lay.red);
-    hipError_t e = vlbm::launch_minima(in, c->plane, c->cur(), dp, blocks, c->p.precision, c->stream);
+    hipError_t e = vlbm::launch_minima(in, c->plane, c->cur(), dp, blocks, c->p.precision, c->blocked,
+                                       c->stream);
     part.resize((size_t)blocks * 2);
     if (e == hipSuccess)
       e = hipMemcpyAsync(part.data(), dp, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream);
@@ -688,7 +698,8 @@ lbm_status lbm_totals(lbm_ctx* c, int32_t inst, double* out) {
   long long b = (n + 255) / 256;
   const int blocks = (int)(b < kTotalsBlocks ? b : kTotalsBlocks);
   double* part = (double*)(c->ws + c->lay.red);
-  hipError_t e = vlbm::launch_totals(in, c->plane, c->cur(), part, blocks, c->p.precision, c->stream);
+  hipError_t e = vlbm::launch_totals(in, c->plane, c->cur(), part, blocks, c->p.precision, c->blocked,
+                                     c->stream);
   std::vector<double> h((size_t)blocks * 8);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream);
@@ -721,8 +732,9 @@ lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!dst) return fail(c, LBM_EINVAL, "destination must be a device pointer");
   if (lbm_status st = require_attached(c)) return st;
-  hipError_t e = hipMemcpyAsync(dst, c->cur(), lbm_state_bytes(c), hipMemcpyDeviceToDevice,
-                                c->stream);
+  hipError_t e = c->blocked ? vlbm::launch_relayout(c->cur(), dst, c->plane, c->p.precision, 0, c->stream)
+                            : hipMemcpyAsync(dst, c->cur(), lbm_state_bytes(c), hipMemcpyDeviceToDevice,
+                                             c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "get_state copy");
   return LBM_OK;
 }
@@ -730,15 +742,17 @@ lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
 lbm_status lbm_set_state(lbm_ctx* c, const void* src) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!src) return fail(c, LBM_EINVAL, "source must be a device pointer");
-  hipError_t e = hipMemcpyAsync(c->cur(), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice,
-                                c->stream);
+  if (src == c->cur() || src == c->other()) return fail(c, LBM_EINVAL, "src must be a caller buffer");
+  hipError_t e = c->blocked ? vlbm::launch_relayout(src, c->cur(), c->plane, c->p.precision, 1, c->stream)
+                            : hipMemcpyAsync(c->cur(), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice,
+                                             c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
   const int slot = (int)(c->step % 3);
   for (int i = 0; i < c->n_inst && e == hipSuccess; ++i)
     e = vlbm::launch_fill_u32((unsigned int*)&c->slots[i].lam[slot], 0u, 2, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_lambda_state(c->sc, c->insts.data(), c->n_inst, c->plane, c->cur(),
-                                  c->slots, slot, c->p.precision, c->stream);
+                                  c->slots, slot, c->p.precision, c->blocked, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "set_state wavespeed");
   c->detached = false;
   return LBM_OK;
@@ -754,6 +768,8 @@ lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst, double* tx, 
   const size_t nb = lbm_state_bytes(c);
   if (s0 < d0 + nb && d0 < s0 + nb) return fail(c, LBM_EINVAL, "src and dst must not overlap");
   if (dst == c->cur()) return fail(c, LBM_EINVAL, "dst must not be the context's current state buffer");
+  if (src == c->cur() || src == c->other() || dst == c->other())
+    return fail(c, LBM_EINVAL, "src and dst must be caller buffers");
   vlbm::StepArgs a = make_args(c, src, dst, (int)(c->step % 3));
   a.theta_x = tx;
   a.theta_y = ty;
@@ -841,6 +857,16 @@ lbm_status lbm_set_instance_boundary(lbm_ctx* c, int32_t inst, int32_t side, con
     }
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+  if (c->blocked && c->has_bnd) {
+    // the kernels that read descriptions take the planar layout: convert the
+    // current state once, through the other buffer (which the next step
+    // overwrites anyway), and stay planar
+    hipError_t e = vlbm::launch_relayout(c->cur(), c->other(), c->plane, c->p.precision, 0, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->cur(), c->other(), lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "state layout");
+    c->blocked = 0;
+  }
   if (c->n_inst > 1) {  // ensembles read the descriptions from the workspace table
     hipError_t e = hipMemcpyAsync(c->ws + c->lay.bndt, c->bnd.data(), sizeof(vlbm::BndDesc) * c->n_inst,
                                   hipMemcpyHostToDevice, c->stream);
@@ -1114,7 +1140,7 @@ extern "C" lbm_status lbm_step_adjoint_theta(lbm_ctx* c, const double* U, const 
     e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
     if (e == hipSuccess)
       e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, c->plane, U, c->slots, scratch,
-                                    LBM_FP64, c->stream);
+                                    LBM_FP64, 0, c->stream);
     // the forward step's lambda^n also covers the Dirichlet states
     if (e == hipSuccess && c->has_dirichlet)
       e = vlbm::launch_bnd_lambda(make_args(c, U, nullptr, scratch), scratch, c->stream);
@@ -1139,7 +1165,7 @@ extern "C" lbm_status lbm_step_adjoint(lbm_ctx* c, const double* U, const double
   hipError_t e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, c->plane, U, c->slots, scratch,
-                                  LBM_FP64, c->stream);
+                                  LBM_FP64, 0, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint wavespeed");
   // theta^n of U with the forward kernel (its state output goes to the
   // context's other buffer, which the next forward step overwrites anyway;
@@ -1178,7 +1204,7 @@ extern "C" lbm_status lbm_init_adjoint(lbm_ctx* c, const double* u0, const doubl
   e = vlbm::launch_fill_u32((unsigned int*)&c->slots[0].lam[scratch], 0u, 2, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_lambda_state(c->sc, c->insts.data(), 1, (long long)c->insts[0].nx * c->insts[0].ny,
-                                  u0, c->slots, scratch, LBM_FP64, c->stream);
+                                  u0, c->slots, scratch, LBM_FP64, 0, c->stream);
   if (e == hipSuccess)
     e = vlbm::launch_adjoint_init(c->sc, c->insts[0], u0, Ub0, u0b, c->slots, scratch, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "init adjoint launch");

@@ -107,7 +107,7 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_params* p, const void* src_dev,
   // that the reduction raised for non-admissible cells of src (they count
   // the step's output cells only, as in a context)
   hipError_t e = vlbm::launch_fill_u32((unsigned int*)sl, 0u, (long long)(sizeof(Slots) / 4), s);
-  if (e == hipSuccess) e = vlbm::launch_lambda_state(sc, &in, 1, cells, src_dev, sl, 0, p->precision, s);
+  if (e == hipSuccess) e = vlbm::launch_lambda_state(sc, &in, 1, cells, src_dev, sl, 0, p->precision, 0, s);
   if (e == hipSuccess)
     e = vlbm::launch_fill_u32((unsigned int*)((char*)base + offsetof(Slots, cnt)), 0u,
                               (long long)(sizeof(sl->cnt) / 4), s);

@@ -7,8 +7,15 @@
 // produces output.  x-neighbours are exchanged with wave-wide lane shifts;
 // the two edge lanes also load the halo column beside the strip and evaluate
 // the faces and bounds that reach across it.  y-neighbours are the rows the
-// lane already holds in registers from the previous iterations.  No LDS and
-// no barrier is used.
+// lane already holds in registers from the previous iterations.  No barrier
+// is used; LDS only receives the rows of the LDS-staged marches.
+//
+// State layouts.  Planar: value q of cell c (row-major over the instance) at
+// q * plane + c.  Blocked (a context's own buffers, single instance of a
+// width that is a multiple of 64): the 20 values of every run of 64 cells
+// of a row lie together, value q of cell c at (c / 64) * 1280 + q * 64 +
+// c % 64, so that one strip row of the state is one contiguous range of
+// memory.  Caller buffers are always planar.
 //
 // Without density bounds (PP, pressure, unlimited, first order) both face
 // factors of a row are known as soon as it arrives, so the march completes
@@ -85,6 +92,12 @@ __device__ __forceinline__ int map_index(int i, int n, int bc) {
     return r < 0 ? r + n : r;
   }
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Element index of value q of cell c in a state of `plane` cells per plane,
+// planar or blocked (see the layouts above).
+__device__ __forceinline__ long long sidx(int q, long long c, long long plane, int blocked) {
+  return blocked ? ((c >> 6) * 1280 + q * 64 + (c & 63)) : q * plane + c;
 }
 
 __device__ __forceinline__ bool in_sponge(const Scheme& s, int i, int j, int nx, int ny) {
@@ -1101,7 +1114,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 // multiple of 64 (every strip full) and that have no boundary descriptions.
 // The loads into LDS are not tracked by the compiler's wait counters:
 // the march waits on the vector-memory counter itself (see the loop head).
-template <class T, class C, int LIMS, bool TH>
+template <class T, class C, int LIMS, bool TH, bool BLK>
 __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in, Slots* sl, int xs,
                                               int ys, int lane, int wave) {
   const Scheme& sc = A.sc;
@@ -1126,13 +1139,23 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
   T* __restrict__ dbase = (T*)A.dst + in.off;
   const long long P = A.plane;
   const unsigned unx = (unsigned)nx;
+  // where value q of this lane's cell in row R goes
+  auto out_at = [&](int q, int R) -> T* {
+    if constexpr (BLK)
+      return dbase + ((long long)R * nx + x0) * 20 + q * 64 + lane;
+    else
+      return &(dbase + q * P)[(unsigned)R * unx + (unsigned)gi];
+  };
 
   extern __shared__ __align__(16) unsigned char dma_lds[];
   unsigned char* ring = dma_lds + wave * kDmaRing * dma_row_bytes<T>();
   // lane's byte offset inside one load of 1024 bytes: planes per load
   constexpr int kPpl = 1024 / (64 * (int)sizeof(T));  // 2 (float64) or 4 (float32)
   constexpr int kLanesPerPlane = 64 / kPpl;
-  const long long lane_elem = (long long)(lane / kLanesPerPlane) * P + (lane % kLanesPerPlane) * (16 / (int)sizeof(T));
+  // planar: plane q + lane / kLanesPerPlane of the group; blocked: the
+  // group's kPpl planes of the strip row lie together
+  const long long lane_elem = BLK ? (long long)lane * (16 / (int)sizeof(T))
+                                  : (long long)(lane / kLanesPerPlane) * P + (lane % kLanesPerPlane) * (16 / (int)sizeof(T));
   // halo: lanes 0-7 bring 16 bytes of planes 0-7 (u, u_1) that hold the
   // west columns x0 - 2 and x0 - 1, lanes 8-15 16 bytes of planes 0-3 and
   // 8-11 (u, u_2) that hold the east columns x0 + 64 and x0 + 65.  Each pair
@@ -1154,15 +1177,19 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
     east1 = b1 - estart;
   }
   const int hq = lane < 8 ? lane : (lane < 12 ? lane - 8 : lane - 4);
-  const long long halo_elem = (long long)hq * P + (lane < 8 ? wstart : estart);
+  const int hcol = lane < 8 ? wstart : estart;
+  const long long halo_elem = BLK ? (long long)(hcol >> 6) * 1280 + hq * 64 + (hcol & 63) : (long long)hq * P + hcol;
 
   // bring row R (wrapped or clamped) into ring buffer b
   auto issue = [&](int R, int b) {
-    const long long ro = (long long)map_index(R, ny, sc.bc_y) * nx;
+    // row offset: the row's first cell of every plane (planar), or its first
+    // 64-cell block (blocked)
+    const long long ro = (long long)map_index(R, ny, sc.bc_y) * nx * (BLK ? 20 : 1);
     unsigned char* dst = ring + b * dma_row_bytes<T>();
 #pragma unroll
     for (int q = 0; q < 20; q += kPpl) {
-      const T* g = sbase + (long long)q * P + ro + x0 + lane_elem;
+      const T* g = BLK ? sbase + ro + (long long)xs * 1280 + q * 64 + lane_elem
+                       : sbase + (long long)q * P + ro + x0 + lane_elem;
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 64 * (int)sizeof(T)), 16, 0, 0);
     }
     if (hlane) {
@@ -1353,15 +1380,13 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
       const C u4n = pM4 + tB * pd4;
       fin[c] = qP[c] + (u4n - tB * qd3[c]);
       if (row1) {
-        const unsigned o = (unsigned)(L - 1) * unx + (unsigned)gi;
-        put(&(dbase + (4 + c) * P)[o], (T)u1n);
-        put(&(dbase + (8 + c) * P)[o], (T)u2n);
-        put(&(dbase + (12 + c) * P)[o], (T)u3n);
+        put(out_at(4 + c, L - 1), (T)u1n);
+        put(out_at(8 + c, L - 1), (T)u2n);
+        put(out_at(12 + c, L - 1), (T)u3n);
       }
       if (row2) {
-        const unsigned o = (unsigned)(L - 2) * unx + (unsigned)gi;
-        put(&(dbase + c * P)[o], (T)fin[c]);
-        put(&(dbase + (16 + c) * P)[o], (T)u4n);
+        put(out_at(c, L - 2), (T)fin[c]);
+        put(out_at(16 + c, L - 2), (T)u4n);
       }
       qP[c] = s;
       qM3[c] = pM3;
@@ -1417,13 +1442,253 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
   if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, n_lmp, n_nf, n_rho);
 }
 
+// ------------------------------------------ short march, LDS-staged
+
+// The march of march_short with the state rows brought in by direct loads
+// into LDS two rows ahead, as in march_lmp_dma (the same ring, halo loads and
+// waits): same arithmetic, evaluation order and results.  It serves the
+// blocked state of a context (single instance, width a multiple of 64, no
+// boundary descriptions), where a strip row is one contiguous range; planar
+// states take march_short.
+template <class T, class C, int LIMS, bool TH, bool BLK>
+__device__ __forceinline__ void march_short_dma(const StepArgs& A, const Inst& in, Slots* sl, int xs,
+                                                int ys, int lane, int wave) {
+  const Scheme& sc = A.sc;
+  const int nx = in.nx, ny = in.ny;
+  const int x0 = xs * 64;
+  const int gi = x0 + lane;
+  const bool first = lane == 0, last = lane == 63;
+  const int y0 = ys * in.strip_h;
+  const int y1 = min(y0 + in.strip_h, ny);
+  const bool sponge = LIMS == 0 && sc.sponge > 0;
+
+  const double lam = __longlong_as_double((long long)sl->lam[A.slot]);
+  const StepConst<T, C> K = step_const<T, C>(sc, lam);
+
+  if (xs == 0 && ys == 0 && lane == 0) {
+    sl->lam[(A.slot + 2) % 3] = 0ull;
+    sl->t[(A.slot + 1) % 3] = sl->t[A.slot] + in.dx / K.a;
+    if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
+  }
+
+  const T* __restrict__ sbase = (const T*)A.src + in.off;
+  T* __restrict__ dbase = (T*)A.dst + in.off;
+  const long long P = A.plane;
+  const unsigned unx = (unsigned)nx;
+  auto out_at = [&](int q, int R) -> T* {
+    if constexpr (BLK)
+      return dbase + ((long long)R * nx + x0) * 20 + q * 64 + lane;
+    else
+      return &(dbase + q * P)[(unsigned)R * unx + (unsigned)gi];
+  };
+
+  extern __shared__ __align__(16) unsigned char dma_lds[];
+  unsigned char* ring = dma_lds + wave * kDmaRing * dma_row_bytes<T>();
+  constexpr int kPpl = 1024 / (64 * (int)sizeof(T));
+  constexpr int kLanesPerPlane = 64 / kPpl;
+  const long long lane_elem = BLK ? (long long)lane * (16 / (int)sizeof(T))
+                                  : (long long)(lane / kLanesPerPlane) * P + (lane % kLanesPerPlane) * (16 / (int)sizeof(T));
+  constexpr int kVpl = 16 / (int)sizeof(T);
+  const bool hlane = lane < 16;
+  int wstart, west1, estart, east0;
+  {
+    const int a2 = map_index(x0 - 2, nx, sc.bc_x), a1 = map_index(x0 - 1, nx, sc.bc_x);
+    wstart = min(a2, a1) / kVpl * kVpl;
+    west1 = a1 - wstart;
+    const int b0 = map_index(x0 + 64, nx, sc.bc_x), b1 = map_index(x0 + 65, nx, sc.bc_x);
+    estart = min(b0, b1) / kVpl * kVpl;
+    east0 = b0 - estart;
+  }
+  const int hq = lane < 8 ? lane : (lane < 12 ? lane - 8 : lane - 4);
+  const int hcol = lane < 8 ? wstart : estart;
+  const long long halo_elem = BLK ? (long long)(hcol >> 6) * 1280 + hq * 64 + (hcol & 63) : (long long)hq * P + hcol;
+  auto issue = [&](int R, int b) {
+    const long long ro = (long long)map_index(R, ny, sc.bc_y) * nx * (BLK ? 20 : 1);
+    unsigned char* dst = ring + b * dma_row_bytes<T>();
+#pragma unroll
+    for (int q = 0; q < 20; q += kPpl) {
+      const T* g = BLK ? sbase + ro + (long long)xs * 1280 + q * 64 + lane_elem
+                       : sbase + (long long)q * P + ro + x0 + lane_elem;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 64 * (int)sizeof(T)), 16, 0, 0);
+    }
+    if (hlane) {
+      const T* g = sbase + halo_elem + ro;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + 20 * 64 * (int)sizeof(T)), 16, 0, 0);
+    }
+  };
+  constexpr int kRowOps = 20 / kPpl + 1;
+
+  C pu[4] = {}, pg[4] = {}, pM3[4] = {}, pd3[4] = {}, pP[4] = {};
+  double lmax = 0.0;
+  unsigned n_bad = 0, n_guard = 0, n_lim = 0, n_cls = 0;
+
+  issue(y0 - 1, 0);
+  issue(y0, 1);
+  int b = 0;
+  for (int L = y0 - 1; L <= y1; ++L) {
+    // the waits of march_lmp_dma: row L was requested at the top of
+    // iteration L - 2; newer are that iteration's 20 stores, row L + 1's
+    // loads and the 20 stores of iteration L - 1, exact where both
+    // iterations stored both of their rows
+    if (!TH && L - 3 >= y0 && L + 1 <= y1)
+      __builtin_amdgcn_s_waitcnt(sizeof(T) == 8 ? 0xCF73 : 0x8F7E);  // vmcnt(40 + kRowOps)
+    else if (L + 1 <= y1)
+      __builtin_amdgcn_s_waitcnt(sizeof(T) == 8 ? 0x0F7B : 0x0F76);  // vmcnt(kRowOps)
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    static_assert(kRowOps == (sizeof(T) == 8 ? 11 : 6), "wait counts of the loop head");
+    __builtin_amdgcn_sched_barrier(0);
+    if (L + 2 <= y1) issue(L + 2, b == 0 ? 2 : b - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    const unsigned char* rb = ring + b * dma_row_bytes<T>();
+    const T* rowv = (const T*)rb;
+    const T* hrow = (const T*)(rb + 20 * 64 * (int)sizeof(T));
+    C u[4], uk[4][4], hu[4], hk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (C)rowv[c * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) uk[k][c] = (C)rowv[(4 + 4 * k + c) * 64 + lane];
+    const int hbase = first ? 0 : 8;
+    const int ein = first ? west1 : east0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      hu[c] = (C)hrow[(hbase + c) * kVpl + ein];
+      hk[c] = (C)hrow[(hbase + 4 + c) * kVpl + ein];
+    }
+
+    C f[4], g[4], hf[4], hg[4];
+    fluxes(u, K.gm1, f, g);
+    fluxes(hu, K.gm1, hf, hg);
+    C M[4][4], d[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        M[k][c] = maxw(k, u[c], f[c], g[c], K.w, K.r2a);
+        d[k][c] = M[k][c] - uk[k][c];
+      }
+    C usx[4], dF[4], M2E[4], d2E[4], usy[4], dG[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C uE = from_right_or(u[c], hu[c]);
+      const C fE = from_right_or(f[c], hf[c]);
+      const C u2E = from_right_or(uk[1][c], hk[c]);
+      M2E[c] = maxw(1, uE, fE, fE, K.w, K.r2a);
+      d2E[c] = M2E[c] - u2E;
+      usx[c] = C(0.5) * (u[c] + uE) - (fE - f[c]) * K.r2k;
+      dF[c] = K.ac * (d[0][c] - d2E[c]);
+      usy[c] = C(0.5) * (pu[c] + u[c]) - (g[c] - pg[c]) * K.r2k;
+      dG[c] = K.ac * (pd3[c] - d[3][c]);
+    }
+    C usw[4], dFw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C hd1 = maxw(0, hu[c], hf[c], hg[c], K.w, K.r2a) - hk[c];
+      usw[c] = C(0.5) * (hu[c] + u[c]) - (f[c] - hf[c]) * K.r2k;
+      dFw[c] = K.ac * (hd1 - d[1][c]);
+    }
+    int gx, gy, gw;
+    const C zero = C(0);
+    double thx = face_theta<LIMS>(sc, usx, dF, K.kappa, zero, zero, zero, zero, gx);
+    double thy = face_theta<LIMS>(sc, usy, dG, K.kappa, zero, zero, zero, zero, gy);
+    double th_edge = face_theta<LIMS>(sc, usw, dFw, K.kappa, zero, zero, zero, zero, gw);
+    if (sponge) {
+      if (in_sponge(sc, gi, L, nx, ny) || in_sponge(sc, gi + 1, L, nx, ny)) thx = 0.0;
+      if (in_sponge(sc, gi, L - 1, nx, ny) || in_sponge(sc, gi, L, nx, ny)) thy = 0.0;
+      if (in_sponge(sc, x0 - 1, L, nx, ny) || in_sponge(sc, x0, L, nx, ny)) th_edge = 0.0;
+    }
+    const bool row0 = L >= y0 && L < y1;
+    const bool row1 = L - 1 >= y0 && L - 1 < y1;
+    if (row0 && !last) {
+      n_guard += gx;
+      n_lim += (thx < 1.0);
+    }
+    if (row0) {
+      n_guard += gy;
+      n_lim += (thy < 1.0);
+    }
+    if (row0 && first) {
+      n_guard += gw;
+      n_lim += (th_edge < 1.0);
+    }
+    if (TH || (LIMS == 0 && A.theta_x)) {
+      if (row0 && first) A.theta_x[(long long)L * (nx + 1) + x0] = th_edge;
+      if (row0) A.theta_x[(long long)L * (nx + 1) + gi + 1] = thx;
+      if ((row0 || row1) && L >= 0 && L <= ny) A.theta_y[(long long)L * nx + gi] = thy;
+    }
+
+    const C tR = (C)thx;
+    const C tL = from_left_or(tR, (C)th_edge);
+    const C tB = (C)thy;
+    C fin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const C o1n = M[0][c] + tR * d[0][c];
+      const C hM1 = maxw(0, hu[c], hf[c], hg[c], K.w, K.r2a);
+      const C hd1 = hM1 - hk[c];
+      const C u1n = from_left_or(o1n, hM1 + tL * hd1);
+      const C u2n = M2E[c] + tR * d2E[c];
+      const C u3n = pM3[c] + tB * pd3[c];
+      C s = K.alpha * u[c];
+      s = s + (u1n - tL * d[1][c]);
+      s = s + (u2n - tR * d[0][c]);
+      s = s + (u3n - tB * d[3][c]);
+      const C u4n = M[3][c] + tB * d[3][c];
+      fin[c] = pP[c] + (u4n - tB * pd3[c]);
+      if (row0) {
+        put(out_at(4 + c, L), (T)u1n);
+        put(out_at(8 + c, L), (T)u2n);
+        put(out_at(12 + c, L), (T)u3n);
+      }
+      if (row1) {
+        put(out_at(c, L - 1), (T)fin[c]);
+        put(out_at(16 + c, L - 1), (T)u4n);
+      }
+      pP[c] = s;
+    }
+    if (row1) {
+      const double l = cell_wavespeed((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2],
+                                      (double)(T)fin[3], sc.gamma);
+      if (l < 0.0) {
+        n_bad += 1;
+        n_cls += bad_class((double)(T)fin[0], (double)(T)fin[1], (double)(T)fin[2], (double)(T)fin[3],
+                           sc.gamma);
+      } else {
+        lmax = vmax(lmax, l);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      pu[c] = u[c];
+      pg[c] = g[c];
+      pM3[c] = M[2][c];
+      pd3[c] = d[2][c];
+    }
+    b = b == 2 ? 0 : b + 1;
+  }
+
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = vmax(lmax, __shfl_xor(lmax, off, 64));
+    n_bad += __shfl_xor(n_bad, off, 64);
+    n_guard += __shfl_xor(n_guard, off, 64);
+    n_lim += __shfl_xor(n_lim, off, 64);
+  }
+  unsigned n_nf, n_rho;
+  reduce_classes(n_cls, n_nf, n_rho);
+  if (lane == 0) publish(sl, (A.slot + 1) % 3, lmax, n_bad, n_guard, n_lim, 0, n_nf, n_rho);
+}
+
 // The step kernel: T the state's storage type, C its arithmetic type, LMP the
 // bounds-limited march, WPE the waves per SIMD the registers are sized for,
 // LIMS a limiter set fixed at compile time (0: read from the scheme) and TH
 // whether the face factors are written (with LIMS = 0 they are written
 // whenever A.theta_x is set), BND whether boundary descriptions are read
-// (only with LIMS = 0).
-template <class T, class C, bool LMP, int WPE, int LIMS, bool TH, bool BND, bool DMA = false>
+// (only with LIMS = 0), DMA the LDS-staged marches, BLK the blocked state
+// layout (with DMA only).
+template <class T, class C, bool LMP, int WPE, int LIMS, bool TH, bool BND, bool DMA = false, bool BLK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void step_kernel(StepArgs A) {
   const int lane = threadIdx.x & 63;
@@ -1450,10 +1715,12 @@ void step_kernel(StepArgs A) {
     const long long local = item - in.item0;
     const int xs = (int)(local % in.xs);
     const int ys = (int)(local / in.xs);
-    if (LMP && DMA)
-      march_lmp_dma<T, C, LIMS, TH>(A, in, A.slots + ii, xs, ys, lane, wave);
-    else if (LMP)
+    if constexpr (LMP && DMA)
+      march_lmp_dma<T, C, LIMS, TH, BLK>(A, in, A.slots + ii, xs, ys, lane, wave);
+    else if constexpr (LMP)
       march_lmp<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
+    else if constexpr (DMA)
+      march_short_dma<T, C, LIMS, TH, BLK>(A, in, A.slots + ii, xs, ys, lane, wave);
     else
       march_short<T, C, LIMS, TH, BND>(A, in, A.slots + ii, xs, ys, lane);
   }
@@ -1635,13 +1902,13 @@ __global__ __launch_bounds__(256) void percell_kernel(StepArgs A) {
 template <class Src, class T>
 __global__ __launch_bounds__(256) void lambda_kernel(const Src* __restrict__ u, long long plane,
                                                      long long n, double gamma, Slots* sl,
-                                                     int slot) {
+                                                     int slot, int blocked) {
   double lmax = 0.0;
   unsigned bad = 0, nf = 0, nr = 0;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
-    const double r = (double)(T)u[c], m1 = (double)(T)u[plane + c],
-                 m2 = (double)(T)u[2 * plane + c], E = (double)(T)u[3 * plane + c];
+    const double r = (double)(T)u[sidx(0, c, plane, blocked)], m1 = (double)(T)u[sidx(1, c, plane, blocked)],
+                 m2 = (double)(T)u[sidx(2, c, plane, blocked)], E = (double)(T)u[sidx(3, c, plane, blocked)];
     const double l = cell_wavespeed(r, m1, m2, E, gamma);
     if (l < 0.0) {
       bad += 1;
@@ -1704,12 +1971,12 @@ __device__ __forceinline__ void dd_add(double& hi, double& lo, double bh, double
 // component and block, part[block][component][2].
 template <class T>
 __global__ __launch_bounds__(256) void totals_kernel(const T* __restrict__ S, long long plane,
-                                                     long long n, double* __restrict__ part) {
+                                                     long long n, double* __restrict__ part, int blocked) {
   double hi[4] = {0.0, 0.0, 0.0, 0.0}, lo[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) dd_add(hi[k], lo[k], (double)S[k * plane + c], 0.0);
+    for (int k = 0; k < 4; ++k) dd_add(hi[k], lo[k], (double)S[sidx(k, c, plane, blocked)], 0.0);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
@@ -1742,12 +2009,12 @@ __global__ __launch_bounds__(256) void totals_kernel(const T* __restrict__ S, lo
 // partial pair per block (+inf where a block has no such cell).
 template <class T>
 __global__ __launch_bounds__(256) void minima_kernel(const T* __restrict__ S, long long plane,
-                                                     long long n, double* __restrict__ part) {
+                                                     long long n, double* __restrict__ part, int blocked) {
   double mr = kHuge, me = kHuge;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
-    const double r = (double)S[c], m1 = (double)S[plane + c], m2 = (double)S[2 * plane + c],
-                 E = (double)S[3 * plane + c];
+    const double r = (double)S[sidx(0, c, plane, blocked)], m1 = (double)S[sidx(1, c, plane, blocked)],
+                 m2 = (double)S[sidx(2, c, plane, blocked)], E = (double)S[sidx(3, c, plane, blocked)];
     if (!isfinite(r) || !isfinite(m1) || !isfinite(m2) || !isfinite(E)) continue;
     mr = vmin(mr, r);
     me = vmin(me, E - 0.5 * (m1 * m1 + m2 * m2) / r);
@@ -1775,7 +2042,7 @@ __global__ __launch_bounds__(256) void minima_kernel(const T* __restrict__ S, lo
 template <class T, class C>
 __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ u0, long long n,
                                                    T* __restrict__ S, long long plane, Scheme sc,
-                                                   const Slots* sl) {
+                                                   const Slots* sl, int blocked) {
   const double lam = __longlong_as_double((long long)sl->lam[0]);
   const StepConst<T, C> K = step_const<T, C>(sc, lam);
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
@@ -1785,21 +2052,34 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ u0
     for (int k = 0; k < 4; ++k) u[k] = (C)(T)u0[k * n + c];
     fluxes(u, K.gm1, f, g);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) S[k * plane + c] = (T)u[k];
+    for (int k = 0; k < 4; ++k) S[sidx(k, c, plane, blocked)] = (T)u[k];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) S[(4 + 4 * q + k) * plane + c] = (T)maxw(q, u[k], f[k], g[k], K.w, K.r2a);
+      for (int k = 0; k < 4; ++k)
+        S[sidx(4 + 4 * q + k, c, plane, blocked)] = (T)maxw(q, u[k], f[k], g[k], K.w, K.r2a);
   }
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void moments_kernel(const T* __restrict__ S, long long plane,
-                                                      long long n, double* __restrict__ out) {
+                                                      long long n, double* __restrict__ out, int blocked) {
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k * n + c] = (double)S[k * plane + c];
+    for (int k = 0; k < 4; ++k) out[k * n + c] = (double)S[sidx(k, c, plane, blocked)];
+  }
+}
+
+// A single instance's state from one layout into the other (n cells, a
+// multiple of 64): to_blocked = 1 planar -> blocked, 0 blocked -> planar.
+template <class T>
+__global__ __launch_bounds__(256) void relayout_kernel(const T* __restrict__ src, T* __restrict__ dst, long long n,
+                                                       int to_blocked) {
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < 20; ++q) dst[sidx(q, c, n, to_blocked)] = src[sidx(q, c, n, !to_blocked)];
   }
 }
 
@@ -1878,9 +2158,9 @@ __global__ __launch_bounds__(256) void bnd_lambda_kernel(StepArgs A, int slot) {
 // for every limiter set with density bounds (fixed at compile time for the
 // LMP and RLMP sets with PP and pressure).  Its LDS (three rows per wave) is
 // dynamic, above the default limit in float64.
-template <class T, int WPE, int LIMS, bool TH>
+template <class T, bool LMP, int WPE, int LIMS, bool TH, bool BLK>
 static void launch_dma(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-  const auto k = step_kernel<T, T, true, WPE, LIMS, TH, false, true>;
+  const auto k = step_kernel<T, T, LMP, WPE, LIMS, TH, false, true, BLK>;
   // the limit is a property of the function on each device: raise it on the
   // first launch on every device (a failure leaves the error for the
   // launcher's hipGetLastError, and the launch itself then fails too)
@@ -1897,32 +2177,45 @@ static void launch_dma(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s) 
   hipLaunchKernelGGL(k, grid, block, (unsigned)dma_lds_bytes<T>((int)block.x / 64), s, a);
 }
 
-static bool dma_ok(const StepArgs& a) {
-#ifdef VLBM_NO_DMA
-  return false;
-#else
-  return a.n_inst == 1 && a.inst0.nx % 64 == 0 && !a.bnd;
-#endif
-}
+static bool dma_ok(const StepArgs& a) { return a.n_inst == 1 && a.inst0.nx % 64 == 0 && !a.bnd; }
 
 template <class T, bool LMP, int WPE>
 static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
+  constexpr int kRelaxed = 1 | 4 | 8;  // (bounds-limited sets only)
+  if (a.blocked) {
+    // a context's blocked state: the LDS-staged marches (the launcher has
+    // checked that the state qualifies)
+    if (lims == kFixed && a.theta_x)
+      launch_dma<T, LMP, WPE, kFixed, true, true>(a, grid, block, s);
+    else if (lims == kFixed)
+      launch_dma<T, LMP, WPE, kFixed, false, true>(a, grid, block, s);
+    else if constexpr (LMP) {
+      if (lims == kRelaxed && a.theta_x)
+        launch_dma<T, LMP, WPE, kRelaxed, true, true>(a, grid, block, s);
+      else if (lims == kRelaxed)
+        launch_dma<T, LMP, WPE, kRelaxed, false, true>(a, grid, block, s);
+      else
+        launch_dma<T, LMP, WPE, 0, false, true>(a, grid, block, s);
+    } else {
+      launch_dma<T, LMP, WPE, 0, false, true>(a, grid, block, s);
+    }
+    return;
+  }
   if constexpr (LMP) {
     if (dma_ok(a)) {
       // PP + LMP + pressure and PP + RLMP + pressure with the set fixed;
       // every other set, and sponge layers, with the set read at run time
-      constexpr int kRelaxed = 1 | 4 | 8;
       if (lims == kFixed && a.theta_x)
-        launch_dma<T, WPE, kFixed, true>(a, grid, block, s);
+        launch_dma<T, LMP, WPE, kFixed, true, false>(a, grid, block, s);
       else if (lims == kFixed)
-        launch_dma<T, WPE, kFixed, false>(a, grid, block, s);
+        launch_dma<T, LMP, WPE, kFixed, false, false>(a, grid, block, s);
       else if (lims == kRelaxed && a.theta_x)
-        launch_dma<T, WPE, kRelaxed, true>(a, grid, block, s);
+        launch_dma<T, LMP, WPE, kRelaxed, true, false>(a, grid, block, s);
       else if (lims == kRelaxed)
-        launch_dma<T, WPE, kRelaxed, false>(a, grid, block, s);
+        launch_dma<T, LMP, WPE, kRelaxed, false, false>(a, grid, block, s);
       else
-        launch_dma<T, WPE, 0, false>(a, grid, block, s);
+        launch_dma<T, LMP, WPE, 0, false, false>(a, grid, block, s);
       return;
     }
   }
@@ -1942,6 +2235,7 @@ hipError_t launch_bnd_lambda(const StepArgs& a, int slot, hipStream_t s) {
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
+  if (a.blocked && !dma_ok(a)) return hipErrorInvalidValue;
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
   const int lims = (a.sc.order == 2 && a.sc.sponge == 0 && a.sc.eps <= 1e-12) ? a.sc.limiters : 0;
   const dim3 block(64 * a.waves_per_group);
@@ -1962,7 +2256,7 @@ hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
 
 hipError_t launch_init(const Scheme& sc, const Inst* insts, int n_inst, const Inst* /*dev*/,
                        long long plane, const double* u0, void* S, Slots* slots, int precision,
-                       hipStream_t s) {
+                       int blocked, hipStream_t s) {
   long long u0_off = 0;
   for (int i = 0; i < n_inst; ++i) {
     const Inst& in = insts[i];
@@ -1970,58 +2264,69 @@ hipError_t launch_init(const Scheme& sc, const Inst* insts, int n_inst, const In
     const double* u = u0 + u0_off;
     if (precision == 0)
       hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for_reduce(n)), dim3(256), 0, s, u,
-                         n, n, sc.gamma, slots + i, 0);
+                         n, n, sc.gamma, slots + i, 0, 0);
     else
       hipLaunchKernelGGL((lambda_kernel<double, float>), dim3(grid_for_reduce(n)), dim3(256), 0, s, u, n,
-                         n, sc.gamma, slots + i, 0);
+                         n, sc.gamma, slots + i, 0, 0);
     if (precision == 0)
       hipLaunchKernelGGL((init_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
-                         (double*)S + in.off, plane, sc, (const Slots*)(slots + i));
+                         (double*)S + in.off, plane, sc, (const Slots*)(slots + i), blocked);
     else
       hipLaunchKernelGGL((init_kernel<float, float>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
-                         (float*)S + in.off, plane, sc, (const Slots*)(slots + i));
+                         (float*)S + in.off, plane, sc, (const Slots*)(slots + i), blocked);
     u0_off += 4 * n;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts, int n_inst, long long plane,
-                               const void* S, Slots* slots, int slot, int precision,
+                               const void* S, Slots* slots, int slot, int precision, int blocked,
                                hipStream_t s) {
   for (int i = 0; i < n_inst; ++i) {
     const Inst& in = insts[i];
     const long long n = (long long)in.nx * in.ny;
     if (precision == 0)
       hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
-                         (const double*)S + in.off, plane, n, sc.gamma, slots + i, slot);
+                         (const double*)S + in.off, plane, n, sc.gamma, slots + i, slot, blocked);
     else
       hipLaunchKernelGGL((lambda_kernel<float, float>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
-                         (const float*)S + in.off, plane, n, sc.gamma, slots + i, slot);
+                         (const float*)S + in.off, plane, n, sc.gamma, slots + i, slot, blocked);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_moments(const Inst& in, long long plane, const void* S, double* out,
-                          int precision, hipStream_t s) {
+                          int precision, int blocked, hipStream_t s) {
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((moments_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, out);
+                       (const double*)S + in.off, plane, n, out, blocked);
   else
     hipLaunchKernelGGL((moments_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, out);
+                       (const float*)S + in.off, plane, n, out, blocked);
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout(const void* src, void* dst, long long n, int precision, int to_blocked,
+                           hipStream_t s) {
+  if (precision == 0)
+    hipLaunchKernelGGL((relayout_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)src,
+                       (double*)dst, n, to_blocked);
+  else
+    hipLaunchKernelGGL((relayout_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s, (const float*)src,
+                       (float*)dst, n, to_blocked);
   return hipGetLastError();
 }
 
 hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
-                         int blocks, int precision, hipStream_t s) {
+                         int blocks, int precision, int blocked, hipStream_t s) {
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((totals_kernel<double>), dim3(blocks), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, part);
+                       (const double*)S + in.off, plane, n, part, blocked);
   else
     hipLaunchKernelGGL((totals_kernel<float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, part);
+                       (const float*)S + in.off, plane, n, part, blocked);
   return hipGetLastError();
 }
 
@@ -2038,14 +2343,14 @@ hipError_t launch_percell(const StepArgs& a, int precision, hipStream_t s) {
 }
 
 hipError_t launch_minima(const Inst& in, long long plane, const void* S, double* part,
-                         int blocks, int precision, hipStream_t s) {
+                         int blocks, int precision, int blocked, hipStream_t s) {
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((minima_kernel<double>), dim3(blocks), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, part);
+                       (const double*)S + in.off, plane, n, part, blocked);
   else
     hipLaunchKernelGGL((minima_kernel<float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, part);
+                       (const float*)S + in.off, plane, n, part, blocked);
   return hipGetLastError();
 }
 

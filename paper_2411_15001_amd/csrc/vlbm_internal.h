@@ -77,6 +77,9 @@ struct StepArgs {
     const BndDesc* bnd_table;
   };
   int bnd;                // 1 if any instance has a boundary description
+  int blocked;            // src and dst hold the blocked layout (a context's own
+                          // buffers; single instance, nx a multiple of 64, no
+                          // boundary descriptions), else planar
   Scheme sc;
 };
 
@@ -84,14 +87,20 @@ enum { BND_ZERO_GRADIENT = 0, BND_WALL = 1, BND_DIRICHLET = 2 };
 
 // Launchers (step.hip).
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s);
+// `blocked`: the state S is in the blocked layout (single instance; see
+// step.hip), else planar.
 hipError_t launch_init(const Scheme& sc, const Inst* insts_host, int n_inst,
                        const Inst* insts_dev, long long plane, const double* u0,
-                       void* S, Slots* slots, int precision, hipStream_t s);
+                       void* S, Slots* slots, int precision, int blocked, hipStream_t s);
 hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_inst,
                                long long plane, const void* S, Slots* slots,
-                               int slot, int precision, hipStream_t s);
+                               int slot, int precision, int blocked, hipStream_t s);
 hipError_t launch_moments(const Inst& in, long long plane, const void* S,
-                          double* out, int precision, hipStream_t s);
+                          double* out, int precision, int blocked, hipStream_t s);
+// A single instance's state of n cells (n a multiple of 64) from src to dst,
+// planar -> blocked (to_blocked = 1) or blocked -> planar (0).
+hipError_t launch_relayout(const void* src, void* dst, long long n, int precision, int to_blocked,
+                           hipStream_t s);
 // Per-cell blending step (an ablation): state A.src -> A.dst with the face
 // factors A.theta_x / A.theta_y of the same state, single instance; also
 // the step's slot bookkeeping.
@@ -99,11 +108,11 @@ hipError_t launch_percell(const StepArgs& a, int precision, hipStream_t s);
 // Block minima of rho and of rho e = E - |m|^2 / (2 rho) over the finite
 // cells of the moment slot, part[blocks][2].
 hipError_t launch_minima(const Inst& in, long long plane, const void* S, double* part,
-                         int blocks, int precision, hipStream_t s);
+                         int blocks, int precision, int blocked, hipStream_t s);
 // Double-double partial totals of the moment slot, part[blocks][4][2]; the
 // grid is `blocks` workgroups of 256 threads.
 hipError_t launch_totals(const Inst& in, long long plane, const void* S, double* part,
-                         int blocks, int precision, hipStream_t s);
+                         int blocks, int precision, int blocked, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t s);
 // Raises each instance's lam[slot] to the largest wavespeed of its Dirichlet
 // boundary states (one workgroup per instance).
