@@ -21,11 +21,15 @@
  * into two state buffers, per-instance scalar slots and counters.  The library
  * allocates only its small host context.  It never allocates device memory.
  *
- * State layout (what lbm_get_state / lbm_set_state / lbm_step_adjoint use):
- * 20 planes, plane q = s*4 + c for slot s in {u, u_1, u_2, u_3, u_4} and
- * component c in {rho, m1, m2, E}; each plane holds the instances one after
- * the other, instance i as [ny_i][nx_i] row-major.  Element type: float64
- * (LBM_FP64) or float32 (LBM_FP32_STATE).
+ * State layout (every caller buffer: lbm_get_state, lbm_set_state,
+ * lbm_step_between, the adjoint, lbm_step_noalloc): 20 planes, plane
+ * q = s*4 + c for slot s in {u, u_1, u_2, u_3, u_4} and component c in
+ * {rho, m1, m2, E}; each plane holds the instances one after the other,
+ * instance i as [ny_i][nx_i] row-major.  Element type: float64 (LBM_FP64)
+ * or float32 (LBM_FP32_STATE).  A context may keep the same values in
+ * another order in its own workspace buffers (a single instance whose width
+ * is a multiple of 64 keeps the 20 values of every 64-cell run of a row
+ * together); the calls that copy to or from caller buffers convert.
  *
  * Streams: every enqueueing call is asynchronous on the stream given to the
  * init call (a hipStream_t passed as void*; NULL = default stream).  A context
@@ -197,13 +201,14 @@ lbm_status lbm_step_theta(lbm_ctx* ctx, double* theta_x_dev, double* theta_y_dev
  * the context's own buffers; theta_x_dev / theta_y_dev as in lbm_step_theta
  * (both NULL: no face output).  The step count, lambda, t and counters
  * advance as for lbm_step, so src_dev must hold the state the context is at:
- * its own current buffer (after lbm_init, lbm_step or lbm_set_state) or the
- * dst_dev of the previous lbm_step_between.  Afterwards the context's current
+ * a copy of its current state (lbm_get_state after lbm_init, lbm_step or
+ * lbm_set_state) or the dst_dev of the previous lbm_step_between.  Afterwards the context's current
  * state lives in dst_dev: lbm_step, lbm_step_graph, lbm_step_theta,
  * lbm_moments, lbm_totals, lbm_get_state and lbm_autotune return LBM_EINVAL
  * until lbm_set_state loads a state again.  For recomputing a segment of a
  * rollout step by step without copying each state out.  Single instance;
- * LBM_EINVAL if src and dst overlap or dst is the context's current buffer.
+ * LBM_EINVAL if src and dst overlap or either is one of the context's own
+ * state buffers.
  * Asynchronous. */
 lbm_status lbm_step_between(lbm_ctx* ctx, const void* src_dev, void* dst_dev,
                             double* theta_x_dev, double* theta_y_dev);
@@ -229,8 +234,10 @@ lbm_status lbm_totals(lbm_ctx* ctx, int32_t inst, double* totals_host);
 lbm_status lbm_diagnostics(lbm_ctx* ctx, int32_t inst, lbm_diag* out);
 
 /* Copy the whole current state (layout above, lbm_state_bytes bytes) to /
- * from caller device memory; set_state also sets lambda^n from the new state
- * (so the next step's a^n follows it) and keeps t and the step count. */
+ * from caller device memory, converting from / to the context's own order;
+ * set_state also sets lambda^n from the new state (so the next step's a^n
+ * follows it) and keeps t and the step count (LBM_EINVAL if src_dev is one
+ * of the context's own state buffers). */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst_dev);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* src_dev);
