@@ -157,8 +157,8 @@ struct lbm_ctx {
   int grid_per_cu = 0;  // 0: one wave per strip; k > 0: persistent grid of k groups per CU
   int n_cu = 256;       // compute units of the context's device
   bool detached = false;  // the current state lives in a caller buffer (lbm_step_between)
-  // the context's own state buffers hold the blocked layout (single
-  // instance, nx a multiple of 64, face blending, no boundary descriptions):
+  // the context's own state buffers hold the blocked layout (every width a
+  // multiple of 64, face blending, no boundary descriptions):
   // a strip row of the state is one contiguous range for the LDS-staged
   // marches.  Caller buffers (lbm_get_state, lbm_set_state,
   // lbm_step_between, the adjoint) are planar; the library converts.
@@ -402,7 +402,8 @@ lbm_status common_init(const lbm_params* p, int n, const int32_t* nx, const int3
   c->p = *p;
   c->sc = make_scheme(p);
   c->n_inst = n;
-  c->blocked = (n == 1 && nx[0] % 64 == 0 && p->blend == LBM_BLEND_FACE) ? 1 : 0;
+  c->blocked = p->blend == LBM_BLEND_FACE ? 1 : 0;
+  for (int i = 0; i < n; ++i) c->blocked &= nx[i] % 64 == 0 ? 1 : 0;
   c->stream = (hipStream_t)stream;
   c->lay = layout(p, n, nx, ny);
   c->ws = (char*)ws;
@@ -732,7 +733,8 @@ lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!dst) return fail(c, LBM_EINVAL, "destination must be a device pointer");
   if (lbm_status st = require_attached(c)) return st;
-  hipError_t e = c->blocked ? vlbm::launch_relayout(c->cur(), dst, c->plane, c->p.precision, 0, c->stream)
+  hipError_t e = c->blocked ? vlbm::launch_relayout(c->insts.data(), c->n_inst, c->plane, c->cur(), dst,
+                                                    c->p.precision, 0, c->stream)
                             : hipMemcpyAsync(dst, c->cur(), lbm_state_bytes(c), hipMemcpyDeviceToDevice,
                                              c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "get_state copy");
@@ -743,7 +745,8 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!src) return fail(c, LBM_EINVAL, "source must be a device pointer");
   if (src == c->cur() || src == c->other()) return fail(c, LBM_EINVAL, "src must be a caller buffer");
-  hipError_t e = c->blocked ? vlbm::launch_relayout(src, c->cur(), c->plane, c->p.precision, 1, c->stream)
+  hipError_t e = c->blocked ? vlbm::launch_relayout(c->insts.data(), c->n_inst, c->plane, src, c->cur(),
+                                                    c->p.precision, 1, c->stream)
                             : hipMemcpyAsync(c->cur(), src, lbm_state_bytes(c), hipMemcpyDeviceToDevice,
                                              c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
@@ -861,7 +864,8 @@ lbm_status lbm_set_instance_boundary(lbm_ctx* c, int32_t inst, int32_t side, con
     // the kernels that read descriptions take the planar layout: convert the
     // current state once, through the other buffer (which the next step
     // overwrites anyway), and stay planar
-    hipError_t e = vlbm::launch_relayout(c->cur(), c->other(), c->plane, c->p.precision, 0, c->stream);
+    hipError_t e = vlbm::launch_relayout(c->insts.data(), c->n_inst, c->plane, c->cur(), c->other(),
+                                         c->p.precision, 0, c->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->cur(), c->other(), lbm_state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "state layout");

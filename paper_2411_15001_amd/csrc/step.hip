@@ -11,11 +11,12 @@
 // is used; LDS only receives the rows of the LDS-staged marches.
 //
 // State layouts.  Planar: value q of cell c (row-major over the instance) at
-// q * plane + c.  Blocked (a context's own buffers, single instance of a
-// width that is a multiple of 64): the 20 values of every run of 64 cells
-// of a row lie together, value q of cell c at (c / 64) * 1280 + q * 64 +
-// c % 64, so that one strip row of the state is one contiguous range of
-// memory.  Caller buffers are always planar.
+// q * plane + c.  Blocked (a context's own buffers when every instance's
+// width is a multiple of 64): each instance's state follows the ones before
+// it (20 values per cell), and inside it the 20 values of every run of 64
+// cells of a row lie together, value q of cell c at (c / 64) * 1280 +
+// q * 64 + c % 64, so that one strip row of the state is one contiguous
+// range of memory.  Caller buffers are always planar.
 //
 // Without density bounds (PP, pressure, unlimited, first order) both face
 // factors of a row are known as soon as it arrives, so the march completes
@@ -94,8 +95,9 @@ __device__ __forceinline__ int map_index(int i, int n, int bc) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
-// Element index of value q of cell c in a state of `plane` cells per plane,
-// planar or blocked (see the layouts above).
+// Element index of value q of cell c of one instance, from the instance's
+// first value, in a state of `plane` cells per plane, planar or blocked (see
+// the layouts above).
 __device__ __forceinline__ long long sidx(int q, long long c, long long plane, int blocked) {
   return blocked ? ((c >> 6) * 1280 + q * 64 + (c & 63)) : q * plane + c;
 }
@@ -1135,8 +1137,10 @@ __device__ __forceinline__ void march_lmp_dma(const StepArgs& A, const Inst& in,
     if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
   }
 
-  const T* __restrict__ sbase = (const T*)A.src + in.off;
-  T* __restrict__ dbase = (T*)A.dst + in.off;
+  // the instance's first value: planar, cell (0, 0) of plane 0; blocked,
+  // its whole state follows the instances before it
+  const T* __restrict__ sbase = (const T*)A.src + in.off * (BLK ? 20 : 1);
+  T* __restrict__ dbase = (T*)A.dst + in.off * (BLK ? 20 : 1);
   const long long P = A.plane;
   const unsigned unx = (unsigned)nx;
   // where value q of this lane's cell in row R goes
@@ -1471,8 +1475,10 @@ __device__ __forceinline__ void march_short_dma(const StepArgs& A, const Inst& i
     if (sc.a_mode == 1 && K.a < 2.0 * lam / (1.0 - sc.alpha)) atomicOr(&sl->cnt[CNT_BOUCHUT], 1ull);
   }
 
-  const T* __restrict__ sbase = (const T*)A.src + in.off;
-  T* __restrict__ dbase = (T*)A.dst + in.off;
+  // the instance's first value: planar, cell (0, 0) of plane 0; blocked,
+  // its whole state follows the instances before it
+  const T* __restrict__ sbase = (const T*)A.src + in.off * (BLK ? 20 : 1);
+  T* __restrict__ dbase = (T*)A.dst + in.off * (BLK ? 20 : 1);
   const long long P = A.plane;
   const unsigned unx = (unsigned)nx;
   auto out_at = [&](int q, int R) -> T* {
@@ -2071,15 +2077,18 @@ __global__ __launch_bounds__(256) void moments_kernel(const T* __restrict__ S, l
   }
 }
 
-// A single instance's state from one layout into the other (n cells, a
-// multiple of 64): to_blocked = 1 planar -> blocked, 0 blocked -> planar.
+// One instance's state (n cells, a multiple of 64, first cell at offset off
+// of every plane of `plane` cells) from one layout into the other:
+// to_blocked = 1 planar -> blocked, 0 blocked -> planar.
 template <class T>
 __global__ __launch_bounds__(256) void relayout_kernel(const T* __restrict__ src, T* __restrict__ dst, long long n,
-                                                       int to_blocked) {
+                                                       long long plane, long long off, int to_blocked) {
+  const T* s = src + off * (to_blocked ? 1 : 20);
+  T* d = dst + off * (to_blocked ? 20 : 1);
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < 20; ++q) dst[sidx(q, c, n, to_blocked)] = src[sidx(q, c, n, !to_blocked)];
+    for (int q = 0; q < 20; ++q) d[sidx(q, c, plane, to_blocked)] = s[sidx(q, c, plane, !to_blocked)];
   }
 }
 
@@ -2184,8 +2193,8 @@ static void launch_step_as(const StepArgs& a, int lims, dim3 grid, dim3 block, h
   constexpr int kFixed = LMP ? (1 | 2 | 8) : (1 | 8);
   constexpr int kRelaxed = 1 | 4 | 8;  // (bounds-limited sets only)
   if (a.blocked) {
-    // a context's blocked state: the LDS-staged marches (the launcher has
-    // checked that the state qualifies)
+    // a context's blocked state: the LDS-staged marches (every instance's
+    // width is a multiple of 64 and no instance has boundary descriptions)
     if (lims == kFixed && a.theta_x)
       launch_dma<T, LMP, WPE, kFixed, true, true>(a, grid, block, s);
     else if (lims == kFixed)
@@ -2235,7 +2244,7 @@ hipError_t launch_bnd_lambda(const StepArgs& a, int slot, hipStream_t s) {
 }
 
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s) {
-  if (a.blocked && !dma_ok(a)) return hipErrorInvalidValue;
+  if (a.blocked && (a.bnd || (a.n_inst == 1 && a.inst0.nx % 64 != 0))) return hipErrorInvalidValue;
   const bool lmp = (a.sc.limiters & 6u) != 0 && a.sc.order == 2;
   const int lims = (a.sc.order == 2 && a.sc.sponge == 0 && a.sc.eps <= 1e-12) ? a.sc.limiters : 0;
   const dim3 block(64 * a.waves_per_group);
@@ -2270,10 +2279,10 @@ hipError_t launch_init(const Scheme& sc, const Inst* insts, int n_inst, const In
                          n, sc.gamma, slots + i, 0, 0);
     if (precision == 0)
       hipLaunchKernelGGL((init_kernel<double, double>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
-                         (double*)S + in.off, plane, sc, (const Slots*)(slots + i), blocked);
+                         (double*)S + in.off * (blocked ? 20 : 1), plane, sc, (const Slots*)(slots + i), blocked);
     else
       hipLaunchKernelGGL((init_kernel<float, float>), dim3(grid_for(n)), dim3(256), 0, s, u, n,
-                         (float*)S + in.off, plane, sc, (const Slots*)(slots + i), blocked);
+                         (float*)S + in.off * (blocked ? 20 : 1), plane, sc, (const Slots*)(slots + i), blocked);
     u0_off += 4 * n;
   }
   return hipGetLastError();
@@ -2287,10 +2296,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts, int n_inst, 
     const long long n = (long long)in.nx * in.ny;
     if (precision == 0)
       hipLaunchKernelGGL((lambda_kernel<double, double>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
-                         (const double*)S + in.off, plane, n, sc.gamma, slots + i, slot, blocked);
+                         (const double*)S + in.off * (blocked ? 20 : 1), plane, n, sc.gamma, slots + i, slot, blocked);
     else
       hipLaunchKernelGGL((lambda_kernel<float, float>), dim3(grid_for_reduce(n)), dim3(256), 0, s,
-                         (const float*)S + in.off, plane, n, sc.gamma, slots + i, slot, blocked);
+                         (const float*)S + in.off * (blocked ? 20 : 1), plane, n, sc.gamma, slots + i, slot, blocked);
   }
   return hipGetLastError();
 }
@@ -2300,21 +2309,24 @@ hipError_t launch_moments(const Inst& in, long long plane, const void* S, double
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((moments_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, out, blocked);
+                       (const double*)S + in.off * (blocked ? 20 : 1), plane, n, out, blocked);
   else
     hipLaunchKernelGGL((moments_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, out, blocked);
+                       (const float*)S + in.off * (blocked ? 20 : 1), plane, n, out, blocked);
   return hipGetLastError();
 }
 
-hipError_t launch_relayout(const void* src, void* dst, long long n, int precision, int to_blocked,
-                           hipStream_t s) {
-  if (precision == 0)
-    hipLaunchKernelGGL((relayout_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)src,
-                       (double*)dst, n, to_blocked);
-  else
-    hipLaunchKernelGGL((relayout_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s, (const float*)src,
-                       (float*)dst, n, to_blocked);
+hipError_t launch_relayout(const Inst* insts, int n_inst, long long plane, const void* src, void* dst,
+                           int precision, int to_blocked, hipStream_t s) {
+  for (int i = 0; i < n_inst; ++i) {
+    const long long n = (long long)insts[i].nx * insts[i].ny;
+    if (precision == 0)
+      hipLaunchKernelGGL((relayout_kernel<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)src,
+                         (double*)dst, n, plane, insts[i].off, to_blocked);
+    else
+      hipLaunchKernelGGL((relayout_kernel<float>), dim3(grid_for(n)), dim3(256), 0, s, (const float*)src,
+                         (float*)dst, n, plane, insts[i].off, to_blocked);
+  }
   return hipGetLastError();
 }
 
@@ -2323,10 +2335,10 @@ hipError_t launch_totals(const Inst& in, long long plane, const void* S, double*
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((totals_kernel<double>), dim3(blocks), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, part, blocked);
+                       (const double*)S + in.off * (blocked ? 20 : 1), plane, n, part, blocked);
   else
     hipLaunchKernelGGL((totals_kernel<float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, part, blocked);
+                       (const float*)S + in.off * (blocked ? 20 : 1), plane, n, part, blocked);
   return hipGetLastError();
 }
 
@@ -2347,10 +2359,10 @@ hipError_t launch_minima(const Inst& in, long long plane, const void* S, double*
   const long long n = (long long)in.nx * in.ny;
   if (precision == 0)
     hipLaunchKernelGGL((minima_kernel<double>), dim3(blocks), dim3(256), 0, s,
-                       (const double*)S + in.off, plane, n, part, blocked);
+                       (const double*)S + in.off * (blocked ? 20 : 1), plane, n, part, blocked);
   else
     hipLaunchKernelGGL((minima_kernel<float>), dim3(blocks), dim3(256), 0, s,
-                       (const float*)S + in.off, plane, n, part, blocked);
+                       (const float*)S + in.off * (blocked ? 20 : 1), plane, n, part, blocked);
   return hipGetLastError();
 }
 

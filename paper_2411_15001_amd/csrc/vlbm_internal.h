@@ -78,8 +78,8 @@ struct StepArgs {
   };
   int bnd;                // 1 if any instance has a boundary description
   int blocked;            // src and dst hold the blocked layout (a context's own
-                          // buffers; single instance, nx a multiple of 64, no
-                          // boundary descriptions), else planar
+                          // buffers; every width a multiple of 64, no boundary
+                          // descriptions), else planar
   Scheme sc;
 };
 
@@ -87,8 +87,8 @@ enum { BND_ZERO_GRADIENT = 0, BND_WALL = 1, BND_DIRICHLET = 2 };
 
 // Launchers (step.hip).
 hipError_t launch_step(const StepArgs& a, int precision, hipStream_t s);
-// `blocked`: the state S is in the blocked layout (single instance; see
-// step.hip), else planar.
+// `blocked`: the state S is in the blocked layout (see step.hip), else
+// planar.
 hipError_t launch_init(const Scheme& sc, const Inst* insts_host, int n_inst,
                        const Inst* insts_dev, long long plane, const double* u0,
                        void* S, Slots* slots, int precision, int blocked, hipStream_t s);
@@ -97,10 +97,10 @@ hipError_t launch_lambda_state(const Scheme& sc, const Inst* insts_host, int n_i
                                int slot, int precision, int blocked, hipStream_t s);
 hipError_t launch_moments(const Inst& in, long long plane, const void* S,
                           double* out, int precision, int blocked, hipStream_t s);
-// A single instance's state of n cells (n a multiple of 64) from src to dst,
-// planar -> blocked (to_blocked = 1) or blocked -> planar (0).
-hipError_t launch_relayout(const void* src, void* dst, long long n, int precision, int to_blocked,
-                           hipStream_t s);
+// Every instance's state (widths multiples of 64) from src to dst, planar ->
+// blocked (to_blocked = 1) or blocked -> planar (0).
+hipError_t launch_relayout(const Inst* insts_host, int n_inst, long long plane, const void* src, void* dst,
+                           int precision, int to_blocked, hipStream_t s);
 // Per-cell blending step (an ablation): state A.src -> A.dst with the face
 // factors A.theta_x / A.theta_y of the same state, single instance; also
 // the step's slot bookkeeping.

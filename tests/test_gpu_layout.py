@@ -116,3 +116,35 @@ def test_graph_replay_and_reductions_on_blocked_state(gpu):
         assert abs(tot[k] - math.fsum(S[k].astype(np.float64).ravel())) <= 4e-16 * abs(tot[k]) + 1e-300
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", [B.LBM_FP64, B.LBM_FP32_STATE])
+def test_ensemble_blocked_layout(prec, gpu):
+    """An ensemble whose widths are all multiples of 64 keeps the blocked
+    layout (each instance's state after the ones before it): every instance
+    equals its own single-instance run (and the oracle in FP64) after 8
+    steps, also when zero-gradient descriptions set on one instance after 3
+    steps switch the whole ensemble to the planar layout."""
+    from paper_2411_15001_amd.solver import BatchSolver
+
+    sizes = [(64, 40), (128, 70), (192, 33)]
+    u0s = [_u0(nx, ny, seed=20 + i) for i, (nx, ny) in enumerate(sizes)]
+    kw = dict(precision=prec, limiters=1 | 2 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+    for switch in (False, True):
+        bs = BatchSolver(u0s, **kw)
+        for k in range(8):
+            if switch and k == 3:
+                bs.set_boundary(1, 2, np.zeros(sizes[1][0], np.uint8))
+            bs.step(1)
+        for i, (nx, ny) in enumerate(sizes):
+            s = Solver(u0s[i], dx=1.0 / nx, **kw)
+            s.step(8)
+            G = bs.moments(i).cpu().numpy()
+            assert np.array_equal(G, s.moments().cpu().numpy()), (switch, i)
+            s.close()
+            if prec == B.LBM_FP64:
+                ocfg = oracle.Config(nx=nx, ny=ny, dx=1.0 / nx, limiters=1 | 2 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+                O, _ = oracle.init(ocfg, u0s[i])
+                O, _, _, _ = oracle.run(ocfg, O, 8)
+                assert np.array_equal(G, O[0:4]), (switch, i)
+        bs.close()
