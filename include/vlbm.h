@@ -280,7 +280,7 @@ lbm_status lbm_init_adjoint(lbm_ctx* ctx, const double* u0_dev,
  * grids (one wave per strip, or a persistent grid of 1, 2 or 4 workgroups
  * per compute unit) and, for ensembles, both strip modes on the context's own
  * problem and keeps the fastest: a first pass times every candidate, then the
- * four fastest are timed again, best of three.  The choice is recorded in a
+ * four fastest are timed again three times, the median decides.  The choice is recorded in a
  * JSON cache file keyed by problem shape (NULL path = no file) as [rows,
  * waves, groups per CU, strip mode]; a cached entry is used without timing
  * (missing trailing values are 0).  The timed launches read the current state and write the

@@ -1003,11 +1003,13 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
     return LBM_OK;
   };
   // first pass: every candidate with about 4 ms of launches; second pass: the
-  // four fastest again, three times each with about 12 ms, interleaved, best
-  // of three (shapes within a few percent of each other are told apart)
+  // four fastest again, three times each with about 12 ms, interleaved, and
+  // the median of the three (shapes within a few percent of each other are
+  // told apart, and a single fast outlier does not decide)
   struct Cand {
     float ms;
     int r, w, g, m;
+    float t[3];
   };
   std::vector<Cand> cands;
   auto bail = [&](lbm_status s2) {
@@ -1025,21 +1027,24 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* path) {
           float ms = -1.0f;
           st = time_shape(r, w, gpc, m, 4.0f, ms);
           if (st != LBM_OK) return bail(st);
-          if (ms >= 0.0f) cands.push_back({ms, r, w, gpc, m});
+          if (ms >= 0.0f) cands.push_back({ms, r, w, gpc, m, {0.0f, 0.0f, 0.0f}});
         }
       }
     }
   }
   std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
   if (cands.size() > 4) cands.resize(4);
-  for (Cand& k : cands) k.ms = 1e30f;
   for (int round = 0; round < 3; ++round) {
     for (Cand& k : cands) {
       float ms = -1.0f;
       st = time_shape(k.r, k.w, k.g, k.m, 12.0f, ms);
       if (st != LBM_OK) return bail(st);
-      k.ms = std::min(k.ms, ms);
+      k.t[round] = ms;
     }
+  }
+  for (Cand& k : cands) {
+    std::sort(k.t, k.t + 3);
+    k.ms = k.t[1];
   }
   for (const Cand& k : cands) {
     if (k.ms < best) {

@@ -130,6 +130,17 @@ def test_ensemble_blocked_layout(prec, gpu):
     sizes = [(64, 40), (128, 70), (192, 33)]
     u0s = [_u0(nx, ny, seed=20 + i) for i, (nx, ny) in enumerate(sizes)]
     kw = dict(precision=prec, limiters=1 | 2 | 8, a_beta=1.1, bc_x=1, bc_y=1)
+    # the ensemble's state round trip through the planar caller layout
+    bs = BatchSolver(u0s, **kw)
+    bs.step(2)
+    S = bs.get_state()
+    b2 = BatchSolver(u0s, **kw)
+    b2.set_state(S)
+    assert gpu.equal(b2.get_state(), S)
+    for i in range(len(sizes)):
+        assert np.array_equal(b2.moments(i).cpu().numpy(), bs.moments(i).cpu().numpy())
+    bs.close()
+    b2.close()
     for switch in (False, True):
         bs = BatchSolver(u0s, **kw)
         for k in range(8):
