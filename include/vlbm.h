@@ -319,7 +319,10 @@ lbm_status lbm_get_strip_mode(const lbm_ctx* ctx, int32_t* mode);
  * states must be admissible (rho > 0, p > 0, finite: LBM_EINVAL otherwise,
  * checked here; a state the caller makes non-admissible later is skipped by
  * lambda^n, and the step's results are then unspecified).  A ghost
- * beyond a corner takes the x-side rule first, then the y-side rule.  Each
+ * beyond a corner reads each side's kind at that side's boundary cell nearest
+ * to it; walls resolve first (the ghost is the mirror image of the ghost or
+ * cell across the wall), then a Dirichlet side, x before y (its state at the
+ * resolved cell, mirrored by the walls crossed), then zero-gradient.  Each
  * step first raises lambda^n by the Dirichlet states, so that a^n satisfies
  * Bouchut's condition for every state the stencil reads.  The caller owns
  * both arrays and keeps them alive while the context steps.  The states may

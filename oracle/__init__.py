@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
 leg of the benchmark use it to check and time the HIP library; nothing on the
 product path imports it.  It shares no code with the HIP library.
 
-Parity unpinned (see vlbm_oracle.h): the event counters and the no-rescaling
-convention when a changes.  The outflow ghost layers, the sponge layer and the
-wall corners are pinned by tests/test_oracle_conventions.py.
+The conventions the paper leaves open (see vlbm_oracle.h: a changing between
+steps, the event counters, the outflow ghost layers, the sponge layer, wall
+and Dirichlet ghosts and their corners) are pinned by
+tests/test_oracle_conventions.py.
 
 Layout conventions (float64 numpy arrays):
   state S   [20, ny, nx]  plane s*4 + c, slot s in (u, u_1, u_2, u_3, u_4),

@@ -15,17 +15,21 @@
  * x-face between cells (i-1, j) and (i, j); theta_y[ny+1][nx], entry (j, i) is
  * the factor of the y-face between cells (i, j-1) and (i, j).
  *
- * Parity unpinned (conventions the paper leaves open; the readings are fixed
- * here but no value printed in the paper or fixed by mathematics checks them):
- * the event counters of orc_info (n_guard, n_limited, n_bad), and evaluating
- * M_k with the current a^n without rescaling the distributions when a
- * changes between steps.  The two zero-gradient ghost layers of outflow
- * boundaries (a copy of the boundary cell's moment slot and all four
- * distributions) and the sponge layer (theta = 0 on every face touching one
- * of the first `sponge` cells of an outflow wall, ghosts included) are pinned
- * by the tests against numpy restatements on explicitly padded fields
- * (Example 3 with theta = 1, Lax-Friedrichs with theta = 0, the LMP factors
- * of the boundary faces from two padded layers).
+ * Conventions the paper leaves open, each pinned by the tests: M_k of step n
+ * takes the current a^n and the distributions are carried over unchanged
+ * when a changes (the multistep finite-difference form of the second-order
+ * scheme, Section 2 and Appendix A, holds to rounding with a changing from
+ * step to step, and fails for the alternatives); the event counters of
+ * orc_info (n_limited and n_guard over the west and south face of every
+ * cell, n_bad and n_lmp over the cells) equal brute-force counts over the
+ * face factors, numpy face states and the new state.  The two zero-gradient
+ * ghost layers of outflow boundaries (a copy of the boundary cell's moment
+ * slot and all four distributions), the sponge layer (theta = 0 on every face
+ * touching one of the first `sponge` cells of an outflow wall, ghosts
+ * included) and the Dirichlet ghosts below are pinned against numpy
+ * restatements on explicitly padded fields (Example 3 with theta = 1,
+ * Lax-Friedrichs with theta = 0, the LMP factors of the boundary faces from
+ * two padded layers).
  *
  * Boundary cells of kind wall or Dirichlet (Section 4.8 imposes boundary
  * states through the Maxwellians of those states and uses a reflective
@@ -34,13 +38,17 @@
  * (normal momentum negated in the moment slot and in every distribution, the
  * two distributions moving along the wall normal exchanged); a Dirichlet
  * ghost holds the given moments u_D with u_k = M_k(u_D; a^n) in both layers.
- * A ghost cell beyond a corner takes the x-side rule first (at the nearest
- * row), then the y-side rule.  lambda^n of a step also covers the Dirichlet
- * states (a^n must satisfy Bouchut's condition for every state the stencil
- * reads); the initial a^0 of orc_init covers u0 only.  Walls, corners
- * included, are pinned by periodic runs of mirror-symmetric data (walls on
- * two opposite sides, and on all four); the Dirichlet ghosts by the
- * uniform-flow and zero-gradient-equivalence checks of the tests.
+ * A ghost cell beyond a corner reads each side's kind at that side's boundary
+ * cell nearest to it; walls resolve first (the ghost is the mirror image of
+ * the ghost or cell across the wall), then a Dirichlet side, x before y (its
+ * state at the resolved cell, mirrored by the walls crossed), then
+ * zero-gradient.  lambda^n of a step also covers the Dirichlet states (a^n
+ * must satisfy Bouchut's condition for every state the stencil reads); the
+ * initial a^0 of orc_init covers u0 only.  Walls, corners included, are
+ * pinned by periodic runs of mirror-symmetric data (walls on two opposite
+ * sides, on all four, and beside Dirichlet sides whose states are mirror
+ * symmetric too); the Dirichlet ghosts, both layers, lambda^n and the
+ * Dirichlet-Dirichlet corners by padded fields as above.
  */
 #ifndef VLBM_ORACLE_H
 #define VLBM_ORACLE_H

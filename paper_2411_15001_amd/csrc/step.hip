@@ -402,49 +402,49 @@ __device__ __forceinline__ BndDesc bnd_desc(const StepArgs& A, const Slots* sl) 
   return A.n_inst > 1 ? A.bnd_table[sl - A.slots] : A.bnd1;
 }
 
+// State of the ghost cell (i, j) of an instance with boundary descriptions.
+// Each side the cell lies beyond has its kind read at its boundary cell
+// nearest to the ghost.  Walls resolve first (the ghost is the mirror image
+// of the cell it faces, so a corner ghost beside a wall is the mirror image
+// of the ghost or cell across it), then a Dirichlet side, x before y (the
+// given state at the resolved cell along that side and its Maxwellians,
+// mirrored by the walls crossed), then zero-gradient sides (the nearest
+// cell).  Periodic axes wrap.
 template <class T, class C>
 __device__ void bnd_cell(const StepArgs& A, const BndDesc& bd, const Inst& in, const T* __restrict__ sbase,
                          long long P, int i, int j, const StepConst<T, C>& K, T out[20]) {
   const Scheme& sc = A.sc;
   const int nx = in.nx, ny = in.ny;
-  bool refl_x = false, refl_y = false;
+  if (sc.bc_x == 0) i = map_index(i, nx, 0);
+  if (sc.bc_y == 0) j = map_index(j, ny, 0);
+  const bool out_x = i < 0 || i >= nx, out_y = j < 0 || j >= ny;
+  const int side_x = i < 0 ? 0 : 1, side_y = j < 0 ? 2 : 3;
+  const int kind_x = out_x && bd.kind[side_x] ? (int)bd.kind[side_x][map_index(j, ny, sc.bc_y)] : BND_ZERO_GRADIENT;
+  const int kind_y = out_y && bd.kind[side_y] ? (int)bd.kind[side_y][map_index(i, nx, sc.bc_x)] : BND_ZERO_GRADIENT;
+  const bool refl_x = out_x && kind_x == BND_WALL, refl_y = out_y && kind_y == BND_WALL;
+  if (refl_x) i = i < 0 ? -1 - i : 2 * nx - 1 - i;
+  if (refl_y) j = j < 0 ? -1 - j : 2 * ny - 1 - j;
   for (int ax = 0; ax < 2; ++ax) {
-    const int n = ax == 0 ? nx : ny;
-    int& idx = ax == 0 ? i : j;
-    if (idx >= 0 && idx < n) continue;
-    if ((ax == 0 ? sc.bc_x : sc.bc_y) == 0) {
-      idx = map_index(idx, n, 0);
-      continue;
-    }
-    const int side = 2 * ax + (idx < 0 ? 0 : 1);
-    const int other = ax == 0 ? map_index(j, ny, sc.bc_y) : i;
+    if (!(ax == 0 ? out_x : out_y) || (ax == 0 ? kind_x : kind_y) != BND_DIRICHLET) continue;
     const int len = ax == 0 ? ny : nx;
-    const int kind = bd.kind[side] ? (int)bd.kind[side][other] : BND_ZERO_GRADIENT;
-    if (kind == BND_DIRICHLET) {
-      const double* st = bd.state[side];
-      C u[4], f[4], g[4];
+    const int at = ax == 0 ? map_index(j, ny, sc.bc_y) : map_index(i, nx, sc.bc_x);
+    const double* st = bd.state[ax == 0 ? side_x : side_y];
+    C u[4], f[4], g[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) u[c] = (C)st[(long long)c * len + other];
-      fluxes(u, K.gm1, f, g);
+    for (int c = 0; c < 4; ++c) u[c] = (C)st[(long long)c * len + at];
+    fluxes(u, K.gm1, f, g);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        out[c] = (T)u[c];
+    for (int c = 0; c < 4; ++c) {
+      out[c] = (T)u[c];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) out[4 + 4 * k + c] = (T)maxw(k, u[c], f[c], g[c], K.w, K.r2a);
-      }
-      if (refl_x) reflect_slots(out, 0);
-      return;
+      for (int k = 0; k < 4; ++k) out[4 + 4 * k + c] = (T)maxw(k, u[c], f[c], g[c], K.w, K.r2a);
     }
-    if (kind == BND_WALL) {
-      idx = idx < 0 ? -1 - idx : 2 * n - 1 - idx;
-      if (ax == 0)
-        refl_x = true;
-      else
-        refl_y = true;
-    } else {
-      idx = idx < 0 ? 0 : n - 1;
-    }
+    if (refl_y) reflect_slots(out, 1);
+    if (refl_x) reflect_slots(out, 0);
+    return;
   }
+  i = map_index(i, nx, sc.bc_x);
+  j = map_index(j, ny, sc.bc_y);
   const unsigned o = (unsigned)j * (unsigned)nx + (unsigned)i;
 #pragma unroll
   for (int q = 0; q < 20; ++q) out[q] = (sbase + q * P)[o];

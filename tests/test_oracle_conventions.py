@@ -1,14 +1,20 @@
-"""Pins of the oracle's boundary conventions (no GPU): the zero-gradient
-ghost layers of Section 4.2 (a copy of every distribution of the boundary
-cell, two layers deep), the sponge layer of Section 4.2 (theta = 0 on every
-face that touches one of the first `sponge` cells of an outflow wall) and the
-corners of reflective walls (Section 4.8).  Each check compares the oracle
-with an independent numpy restatement on an explicitly padded field, or with
-a periodic run that the walls must reproduce, and is chosen so that the
-plausible alternative readings fail it: a ghost holding the equilibrium
-M_k(u_edge) instead of a copy, a single ghost layer, a sponge one cell
-thinner or thicker, theta = 0 only between two sponge cells, a corner ghost
-that is not the double mirror image."""
+"""Pins of the oracle's conventions where the paper leaves a choice (no
+GPU): the zero-gradient ghost layers of Section 4.2 (a copy of every
+distribution of the boundary cell, two layers deep), the sponge layer of
+Section 4.2 (theta = 0 on every face that touches one of the first `sponge`
+cells of an outflow wall), the ghosts of reflective walls and Dirichlet sides
+and their corners (Section 4.8), the kinetic speed changing between steps
+(M_k with the current a^n, distributions carried over unchanged), and the
+step's event counters.  Each check compares the oracle with an independent
+numpy restatement on an explicitly padded field, with a periodic run that
+walls must reproduce, with the multistep finite-difference form of the
+second-order scheme (Section 2, Appendix A), or with brute-force counts, and
+is chosen so that the plausible alternatives fail it: a ghost holding the
+equilibrium M_k(u_edge) instead of a copy, a single ghost layer, a sponge one
+cell thinner or thicker, theta = 0 only between two sponge cells, a corner
+ghost that is not the mirror image, Dirichlet ghosts with the interior's
+speed or copied distributions, distributions rescaled when a changes, fluxes
+weighted with the previous step's speed, counts over other faces."""
 import numpy as np
 import pytest
 
@@ -298,3 +304,451 @@ def test_walls_on_four_sides_equal_quarter_of_periodic_run(orc, lims):
     assert max(mx, my) < 1e-11 * np.abs(Sp).max()
     if lims & 4:
         assert n_lim > 0
+
+
+# ------------------------ the kinetic speed changing between steps (Section 2)
+def _at(q, di, dj):
+    """Periodic value at (i + di, j + dj) of a [..., ny, nx] field."""
+    return np.roll(np.roll(q, -di, axis=-1), -dj, axis=-2)
+
+
+def _A_a(u):
+    return 0.25 * (_at(u, 1, 0) + _at(u, -1, 0) + _at(u, 0, 1) + _at(u, 0, -1))
+
+
+def _A_d(u):
+    # the mean of the four diagonal neighbours
+    return 0.25 * (_at(u, 1, 1) + _at(u, -1, 1) + _at(u, 1, -1) + _at(u, -1, -1))
+
+
+def _A_d_as_printed(u):
+    # the printed definition lists (i - 1, j + 1) twice and omits (i + 1, j - 1)
+    return 0.25 * (_at(u, 1, 1) + _at(u, -1, 1) + _at(u, -1, 1) + _at(u, -1, -1))
+
+
+def _multistep_residual(U, A, alpha, n, A_d=_A_d):
+    """Largest entry of the left-hand side of the multistep finite-difference
+    form of the second-order D2Q5 scheme (Section 2, the proof of consistency:
+    eq. multistep_FD with the operators of eq. A_ad), evaluated on the moment
+    fields U[n .. n + 5] with the kinetic speed A[m] of the step m -> m + 1,
+    relative to the largest moment."""
+    u = U[n:n + 6]
+    fx = [npref.euler_flux(U[n + k], GAMMA) for k in range(5)]
+
+    def D_x(f):
+        return 0.5 * (_at(f, 1, 0) - _at(f, -1, 0))
+
+    def D_y(g):
+        return 0.5 * (_at(g, 0, 1) - _at(g, 0, -1))
+
+    def Db_x(f):
+        d = D_x(f)
+        return (_at(d, 0, -1) + d + _at(d, 0, 1)) / 3.0
+
+    def Db_y(g):
+        d = D_y(g)
+        return (_at(d, -1, 0) + d + _at(d, 1, 0)) / 3.0
+
+    d41, d32 = u[4] - u[1], u[3] - u[2]
+    r = u[5] + (4.0 * _A_a(d41) - d41) + (4.0 * A_d(d32) - 4.0 * _A_a(d32) + 2.0 * d32) - u[0]
+    r += 2.0 * (D_x(fx[4][0]) / A[n + 4] + 3.0 * Db_x(fx[3][0]) / A[n + 3]
+                + 3.0 * Db_x(fx[2][0]) / A[n + 2] + D_x(fx[1][0]) / A[n + 1])
+    r += 2.0 * (D_y(fx[4][1]) / A[n + 4] + 3.0 * Db_y(fx[3][1]) / A[n + 3]
+                + 3.0 * Db_y(fx[2][1]) / A[n + 2] + D_y(fx[1][1]) / A[n + 1])
+    r += 2.0 * (1.0 - alpha) * ((d41 - _A_a(d41)) + (3.0 * _A_a(d32) - 2.0 * A_d(d32) - d32))
+    return np.abs(r).max() / max(np.abs(u[0]).max(), np.abs(u[5]).max())
+
+
+def _smooth_moments(n):
+    xs = cases.cell_centres(n)[None, :]
+    ys = cases.cell_centres(n)[:, None]
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * xs) * np.cos(2 * np.pi * ys)
+    v1 = 0.5 + 0.2 * np.cos(2 * np.pi * ys) + 0 * xs
+    v2 = -0.3 + 0.1 * np.sin(2 * np.pi * xs) + 0 * ys
+    p = 1.0 + 0.2 * np.cos(2 * np.pi * (xs + ys))
+    return cases.prim_to_cons(rho, v1, v2, p, GAMMA)
+
+
+_PER_STEP_A = [12.0, 15.0, 11.0, 14.0, 12.5, 16.0, 13.0, 12.0]
+
+
+def _moment_sequence(orc, n, alpha, speeds, rescale=False):
+    """Moment fields u^0 .. u^len(speeds) of the unlimited scheme (theta = 1)
+    with the kinetic speed of step m set to speeds[m] (None: the dynamic
+    a^m = 2 beta lambda^m / (1 - alpha), beta = 1.3).  rescale plants the
+    alternative convention: when a changes, the non-equilibrium part
+    u_k - M_k(u; a_old) is kept and M_k(u; a_new) put back under it."""
+    cfg = orc.Config(nx=n, ny=n, limiters=0, alpha=alpha, a_beta=1.3)
+    S, _ = orc.init(cfg, _smooth_moments(n))
+    U, A, prev = [S[0:4].copy()], [], None
+    for sp in speeds:
+        c = cfg if sp is None else orc.Config(nx=n, ny=n, limiters=0, alpha=alpha, a_mode=orc.A_FIXED,
+                                             a_fixed=sp)
+        a = orc.kinetic_speed(c, orc.lam(c, S)[0])
+        if rescale and prev is not None and a != prev:
+            Mo = npref.maxwellians(S[0:4], GAMMA, alpha, prev)
+            Mn = npref.maxwellians(S[0:4], GAMMA, alpha, a)
+            for k in range(4):
+                S[4 + 4 * k:8 + 4 * k] += Mn[k] - Mo[k]
+        S, _, _, info = orc.step(c, S)
+        assert info.a == a
+        U.append(S[0:4].copy())
+        A.append(a)
+        prev = a
+    return U, A
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.7])
+@pytest.mark.parametrize("speeds", ["dynamic", "per_step"])
+def test_multistep_identity_with_changing_kinetic_speed(orc, alpha, speeds):
+    """The second-order scheme (theta = 1) obeys its multistep
+    finite-difference form exactly, each flux term divided by the kinetic
+    speed of its own step, when M_k of step n takes a^n and the distributions
+    are carried over unchanged when a changes: the residual stays at
+    rounding level for the dynamic speed and for speeds that jump by up to a
+    third from one step to the next."""
+    sp = [None] * 8 if speeds == "dynamic" else _PER_STEP_A
+    U, A = _moment_sequence(orc, 24, alpha, sp)
+    if speeds == "dynamic":
+        assert len(set(A)) == len(A)  # a does change every step
+    for n in range(3):
+        assert _multistep_residual(U, A, alpha, n) <= 1e-13, n
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.7])
+def test_multistep_identity_rejects_other_conventions(orc, alpha):
+    """The identity tells the conventions apart: rescaling the distributions
+    to the new speed, weighting each flux with the previous step's speed, or
+    the printed form of A_d (one diagonal neighbour twice) each leave a
+    residual of 1e-4 and more, nine orders above rounding."""
+    U, A = _moment_sequence(orc, 24, alpha, _PER_STEP_A)
+    Ur, Ar = _moment_sequence(orc, 24, alpha, _PER_STEP_A, rescale=True)
+    Aprev = [A[0]] + A[:-1]
+    for n in range(3):
+        assert _multistep_residual(Ur, Ar, alpha, n) > 1e-5, n
+        assert _multistep_residual(U, Aprev, alpha, n) > 1e-5, n
+        assert _multistep_residual(U, A, alpha, n, A_d=_A_d_as_printed) > 1e-5, n
+
+
+# ------------------------------------------------------------ step counters
+def _outside_G(us):
+    r0, m1, m2, E = us
+    g0 = m1 * m1 + m2 * m2 - 2.0 * r0 * E
+    return ~(r0 > 0) | ~(g0 < 0)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_limited_faces_are_counted_once_per_cell(orc, bc):
+    """n_limited counts the faces with theta < 1 among the west and south
+    faces of the cells, so each face between two cells once and, on outflow
+    axes, the west and south boundary faces but not the east and north ones.
+    Counting every face of the theta arrays (the periodic wrap face twice,
+    or both outflow boundary faces) gives another number here."""
+    n = 40
+    cfg = orc.Config(nx=n, ny=n, limiters=1 | 4 | 8, bc_x=bc, bc_y=bc)
+    S, _ = orc.init(cfg, cases.riemann4(n, seed=5))
+    for _ in range(15):
+        S, _, _, _ = orc.step(cfg, S)
+    _, tx, ty, info = orc.step(cfg, S)
+    own = int(np.count_nonzero(tx[:, :n] < 1) + np.count_nonzero(ty[:n, :] < 1))
+    assert info.n_limited == own
+    assert np.count_nonzero(tx[:, n] < 1) + np.count_nonzero(ty[n, :] < 1) > 0
+
+
+def test_lmp_check_counts_cells_outside_their_bounds(orc):
+    """n_lmp counts the cells whose new density leaves the eq. (29) bounds of
+    the old state by more than a relative 1e-12; under the relaxed bounds of
+    Section 3.3.2 some do, and the count equals the numpy count."""
+    n = 40
+    cfg = orc.Config(nx=n, ny=n, limiters=1 | 4 | 8)
+    S, _ = orc.init(cfg, cases.riemann4(n, seed=5))
+    for _ in range(15):
+        S, _, _, _ = orc.step(cfg, S)
+    S1, _, _, info = orc.step(cfg, S)
+    mu, nu = npref.lmp_bounds(S, GAMMA, 0.5, info.a)
+    r = S1[0]
+    out = (r < mu - 1e-12 * np.abs(mu)) | (r > nu + 1e-12 * np.abs(nu))
+    assert info.n_lmp == int(np.count_nonzero(out)) > 0
+
+
+@pytest.mark.parametrize("case,fac", [("rarefaction", 0.1), ("riemann4", 0.05), ("riemann4", 0.02)])
+def test_guard_and_bad_counts(orc, case, fac):
+    """Below Bouchut's speed the face states leave the admissible set: every
+    face whose u* (eq. (12)) has rho* <= 0 or non-negative gamma0 takes
+    theta = 0 and is counted once in n_guard, and n_bad counts the new cells
+    with rho <= 0, p <= 0 or a non-finite component; both equal numpy counts
+    on the periodic grid."""
+    n = 40
+    u0 = cases.double_rarefaction(n, seed=0) if case == "rarefaction" else cases.riemann4(n, seed=5)
+    cfg0 = orc.Config(nx=n, ny=n, limiters=1 | 8)
+    S, _ = orc.init(cfg0, u0)
+    for _ in range(3):
+        S, _, _, _ = orc.step(cfg0, S)
+    a = fac * 2.0 * orc.lam(cfg0, S)[0] / 0.5
+    cfg = orc.Config(nx=n, ny=n, limiters=1 | 8, a_mode=orc.A_FIXED, a_fixed=a)
+    S1, tx, ty, info = orc.step(cfg, S)
+    usx, usy, _, _ = npref.faces(S, GAMMA, 0.5, a)
+    gx, gy = _outside_G(usx), _outside_G(usy)
+    assert info.n_guard == int(np.count_nonzero(gx) + np.count_nonzero(gy)) > 0
+    # tx[:, i + 1] and ty[j + 1] are the faces i + 1/2 and j + 1/2
+    assert np.all(tx[:, 1:][gx] == 0) and np.all(ty[1:, :][gy] == 0)
+    with np.errstate(all="ignore"):
+        p = npref.pressure(S1[0:4], GAMMA)
+        bad = ~np.isfinite(S1[0:4]).all(axis=0) | ~(S1[0] > 0) | ~(p > 0)
+    assert info.n_bad == int(np.count_nonzero(bad))
+
+
+# ----------------------------------------- Dirichlet ghost cells (Sec. 4.8)
+def _boundary_states(length, seed, wide=False):
+    """Seeded admissible states along one side: by default faster than the
+    interior of nonequilibrium_state, so that they decide lambda^n; wide
+    spreads density, velocity and pressure further."""
+    rng = np.random.default_rng(seed)
+    if wide:
+        rho = 0.2 + 2.0 * rng.random(length)
+        v1 = 2.0 * rng.uniform(-1, 1, length)
+        v2 = 2.0 * rng.uniform(-1, 1, length)
+        p = 0.3 + 2.0 * rng.random(length)
+    else:
+        rho = 0.8 + 0.4 * rng.random(length)
+        v1 = 1.5 * rng.uniform(-1, 1, length)
+        v2 = 1.5 * rng.uniform(-1, 1, length)
+        p = 0.8 + 0.6 * rng.random(length)
+    return np.ascontiguousarray(cases.prim_to_cons(rho, v1, v2, p, GAMMA))
+
+
+def _dirichlet_config(orc, nx, ny, axis, lo, hi, **kw):
+    L = ny if axis == 0 else nx
+    kinds, states = [None] * 4, [None] * 4
+    s0, s1 = (orc.WEST, orc.EAST) if axis == 0 else (orc.SOUTH, orc.NORTH)
+    kinds[s0] = np.full(L, orc.BND_DIRICHLET, np.uint8)
+    kinds[s1] = np.full(L, orc.BND_DIRICHLET, np.uint8)
+    states[s0], states[s1] = lo, hi
+    bc_x, bc_y = (1, 0) if axis == 0 else (0, 1)
+    return orc.Config(nx=nx, ny=ny, bc_x=bc_x, bc_y=bc_y, bnd_kind=tuple(kinds), bnd_state=tuple(states), **kw)
+
+
+def _pad_dirichlet(S, width, axis, lo, hi, a, alpha=0.5):
+    """S [20, ny, nx] extended by `width` ghost layers: wrapped along the
+    periodic axis; along `axis` every ghost holds the given moments u_D of its
+    row (column) and the distributions M_k(u_D; a)."""
+    bc_x, bc_y = (1, 0) if axis == 0 else (0, 1)
+    Sp = npref.pad(S, width, bc_x, bc_y)
+    for st, sl in ((lo, slice(0, width)), (hi, slice(-width, None))):
+        stp = np.pad(st, [(0, 0), (width, width)], mode="wrap")
+        M = npref.maxwellians(stp, GAMMA, alpha, a)
+        g = np.concatenate([stp] + [M[k] for k in range(4)])
+        if axis == 0:
+            Sp[:, :, sl] = g[:, :, None]
+        else:
+            Sp[:, sl, :] = g[:, None, :]
+    return Sp
+
+
+def _example3(Sp, a):
+    """Example 3 on a padded field, u_5 recovered from the moment slot."""
+    u5 = Sp[0:4] - Sp[4:8] - Sp[8:12] - Sp[12:16] - Sp[16:20]
+    un, uk, _ = npref.second_order_kinetic(Sp, u5, GAMMA, 0.5, a)
+    return np.concatenate([un] + list(uk))
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_dirichlet_ghosts_second_and_first_order(orc, axis):
+    """Dirichlet sides on one axis (the other periodic), distributions out of
+    equilibrium in the interior: lambda^n is the largest wavespeed over the
+    cells and the boundary states; one unlimited step (theta = 1) equals
+    Example 3 on the field padded with ghosts holding u_D and M_k(u_D; a^n),
+    and one first-order step the Lax-Friedrichs update of the padded moments.
+    Ghost distributions taken with the speed of the interior alone, or copied
+    from the edge cells, change the streamed values by tens of percent."""
+    nx, ny = 18, 14
+    S = nonequilibrium_state(nx, ny, seed=12)
+    L = ny if axis == 0 else nx
+    lo, hi = _boundary_states(L, 1), _boundary_states(L, 2)
+    cfg = _dirichlet_config(orc, nx, ny, axis, lo, hi, limiters=0)
+    S1, tx, ty, info = orc.step(cfg, S)
+    assert np.all(tx == 1) and np.all(ty == 1)
+    lam_int = npref.wavespeed(S[0:4], GAMMA)
+    lam_all = max(lam_int, npref.wavespeed(lo, GAMMA), npref.wavespeed(hi, GAMMA))
+    assert lam_all > 1.2 * lam_int
+    assert abs(info.lam - lam_all) <= 1e-15 * lam_all
+    ref = _example3(_pad_dirichlet(S, 1, axis, lo, hi, info.a), info.a)[:, 1:-1, 1:-1]
+    for q in range(20):
+        assert rel(S1[q], ref[q]) <= 1e-12, q
+    # ghost distributions with the interior's speed
+    Sa = _pad_dirichlet(S, 1, axis, lo, hi, 2.0 * lam_int / 0.5)
+    alt = _example3(Sa, info.a)[:, 1:-1, 1:-1]
+    assert max(rel(S1[q], alt[q]) for q in range(20)) > 0.1
+    # ghost distributions copied from the edge cells (zero gradient)
+    Sz = _pad_dirichlet(S, 1, axis, lo, hi, info.a)
+    Se = npref.pad(S, 1, *((1, 0) if axis == 0 else (0, 1)))
+    if axis == 0:
+        Sz[4:20, :, [0, -1]] = Se[4:20, :, [0, -1]]
+    else:
+        Sz[4:20, [0, -1], :] = Se[4:20, [0, -1], :]
+    alt = _example3(Sz, info.a)[:, 1:-1, 1:-1]
+    assert max(rel(S1[q], alt[q]) for q in range(20)) > 0.1
+    # first order
+    S1f, _, _, i1 = orc.step(_dirichlet_config(orc, nx, ny, axis, lo, hi, order=1), S)
+    up = _pad_dirichlet(S, 1, axis, lo, hi, i1.a)[0:4]
+    assert rel(S1f[0:4], npref.lf_first_order(up, GAMMA, 0.5, i1.a)[:, 1:-1, 1:-1]) <= 1e-13
+
+
+def test_dirichlet_two_ghost_layers_in_lmp_bounds(orc):
+    """LMP limiting alone with Dirichlet south and north sides: the factor of
+    every face, boundary faces included, equals min(1, theta^rho_LMP) from the
+    eq. (29) bounds of the field padded with two Dirichlet layers.  The outer
+    layer enters only through the bounds of the first ghost, which decide a
+    boundary face where they bind; in this seeded case they do, and an outer
+    layer copied from the edge cells instead moves a boundary factor by 0.3."""
+    nx, ny = 18, 14
+    S = nonequilibrium_state(nx, ny, seed=223, amp=0.5)
+    lo, hi = _boundary_states(nx, 323, wide=True), _boundary_states(nx, 423, wide=True)
+    cfg = _dirichlet_config(orc, nx, ny, 1, lo, hi, limiters=orc.RHO_LMP)
+    _, tx, ty, info = orc.step(cfg, S)
+    assert info.n_guard == 0
+    kappa = 0.5 * info.a * 0.5
+    sl_j, sl_i, sl_r = slice(2, 2 + ny), slice(1, 2 + nx), slice(2, 3 + nx)
+    sy_j, sy_i, sy_r = slice(1, 2 + ny), slice(2, 2 + nx), slice(2, 3 + ny)
+
+    def factors(Sp):
+        usx, usy, dF, dG = npref.faces(Sp, GAMMA, 0.5, info.a)
+        mu, nu = npref.lmp_bounds(Sp, GAMMA, 0.5, info.a)
+        return (npref.theta_lmp(usx[0][sl_j, sl_i], dF[0][sl_j, sl_i], kappa, mu[sl_j, sl_i], nu[sl_j, sl_i],
+                                mu[sl_j, sl_r], nu[sl_j, sl_r]),
+                npref.theta_lmp(usy[0][sy_j, sy_i], dG[0][sy_j, sy_i], kappa, mu[sy_j, sy_i], nu[sy_j, sy_i],
+                                mu[sy_r, sy_i], nu[sy_r, sy_i]))
+
+    good = _pad_dirichlet(S, 2, 1, lo, hi, info.a)
+    fx, fy = factors(good)
+    assert np.abs(tx - fx).max() <= 1e-9 and np.abs(ty - fy).max() <= 1e-9
+    bnd = np.concatenate([ty[0], ty[-1]])
+    assert np.count_nonzero(bnd < 1.0) >= bnd.size // 4
+    bad = good.copy()
+    edge = npref.pad(S, 2, 0, 1)
+    bad[:, 0, :], bad[:, -1, :] = edge[:, 0, :], edge[:, -1, :]
+    bx, by = factors(bad)
+    assert max(np.abs(tx - bx).max(), np.abs(ty - by).max()) > 0.1
+
+
+def _pad_dirichlet_four(S, lx, hx, ly, hy, a, x_side_last=True):
+    """S padded by two Dirichlet layers on all four sides.  A corner ghost
+    takes the x side's state of the nearest row when x_side_last (the x
+    sides written over the y sides), else the y side's of the nearest
+    column."""
+    Sp = npref.pad(S, 2, 1, 1)
+
+    def ghosts(st):
+        stp = np.pad(st, [(0, 0), (2, 2)], mode="edge")  # nearest row / column
+        M = npref.maxwellians(stp, GAMMA, 0.5, a)
+        return np.concatenate([stp] + [M[k] for k in range(4)])
+
+    def put_y():
+        Sp[:, 0:2, :] = ghosts(ly)[:, None, :]
+        Sp[:, -2:, :] = ghosts(hy)[:, None, :]
+
+    def put_x():
+        Sp[:, :, 0:2] = ghosts(lx)[:, :, None]
+        Sp[:, :, -2:] = ghosts(hx)[:, :, None]
+
+    for put in ((put_y, put_x) if x_side_last else (put_x, put_y)):
+        put()
+    return Sp
+
+
+@pytest.mark.parametrize("seed", [3, 4, 7])
+def test_dirichlet_corner_ghosts(orc, seed):
+    """Dirichlet states on all four sides, LMP limiting alone: every face
+    factor equals the numpy one on the field padded with two Dirichlet
+    layers whose corner ghosts hold the x side's state of the nearest row.
+    The corners enter the bounds of the ghosts beside them; in these seeded
+    cases taking the y side's state there instead changes a boundary factor
+    by more than 0.1."""
+    nx, ny = 18, 14
+    S = nonequilibrium_state(nx, ny, seed=500 + seed, amp=0.5)
+    lx, hx = _boundary_states(ny, 600 + seed, wide=True), _boundary_states(ny, 700 + seed, wide=True)
+    ly, hy = _boundary_states(nx, 800 + seed, wide=True), _boundary_states(nx, 900 + seed, wide=True)
+    kinds = (np.full(ny, orc.BND_DIRICHLET, np.uint8), np.full(ny, orc.BND_DIRICHLET, np.uint8),
+             np.full(nx, orc.BND_DIRICHLET, np.uint8), np.full(nx, orc.BND_DIRICHLET, np.uint8))
+    cfg = orc.Config(nx=nx, ny=ny, limiters=orc.RHO_LMP, bc_x=1, bc_y=1, bnd_kind=kinds,
+                     bnd_state=(lx, hx, ly, hy))
+    _, tx, ty, info = orc.step(cfg, S)
+    assert info.n_guard == 0
+    kappa = 0.5 * info.a * 0.5
+    sl_j, sl_i, sl_r = slice(2, 2 + ny), slice(1, 2 + nx), slice(2, 3 + nx)
+    sy_j, sy_i, sy_r = slice(1, 2 + ny), slice(2, 2 + nx), slice(2, 3 + ny)
+
+    def factors(Sp):
+        usx, usy, dF, dG = npref.faces(Sp, GAMMA, 0.5, info.a)
+        mu, nu = npref.lmp_bounds(Sp, GAMMA, 0.5, info.a)
+        return (npref.theta_lmp(usx[0][sl_j, sl_i], dF[0][sl_j, sl_i], kappa, mu[sl_j, sl_i], nu[sl_j, sl_i],
+                                mu[sl_j, sl_r], nu[sl_j, sl_r]),
+                npref.theta_lmp(usy[0][sy_j, sy_i], dG[0][sy_j, sy_i], kappa, mu[sy_j, sy_i], nu[sy_j, sy_i],
+                                mu[sy_r, sy_i], nu[sy_r, sy_i]))
+
+    fx, fy = factors(_pad_dirichlet_four(S, lx, hx, ly, hy, info.a))
+    assert max(np.abs(tx - fx).max(), np.abs(ty - fy).max()) <= 1e-9
+    bx, by = factors(_pad_dirichlet_four(S, lx, hx, ly, hy, info.a, x_side_last=False))
+    assert max(np.abs(tx - bx).max(), np.abs(ty - by).max()) > 0.1
+
+
+# ----------------------------- corners of walls with Dirichlet sides (Sec. 4.8)
+def _mirror_states(st, axis):
+    """Mirror image of boundary states [4, len] along their side: reversed
+    order, the momentum along the side (normal to the mirror) negated."""
+    m = st[:, ::-1].copy()
+    m[1 + axis] = -m[1 + axis]
+    return m
+
+
+@pytest.mark.parametrize("lims", [1 | 8, 4 | 8, 1 | 4 | 8])
+@pytest.mark.parametrize("wall_axis", [0, 1])
+def test_walls_beside_dirichlet_sides_equal_half_of_periodic_run(orc, lims, wall_axis):
+    """Walls on one axis, Dirichlet states (with momentum along their side)
+    on the other: 30 steps equal, to round-off, the half of the run that is
+    periodic across the walls' axis on twice the length, whose data and
+    Dirichlet states are mirror symmetric about the middle line.  The corner
+    ghosts decide it: beside a wall a corner ghost must be the mirror image
+    of the Dirichlet ghost across it (walls resolve first), which the periodic
+    run has there; the other order (Dirichlet state unmirrored at the
+    nearest row) fails it where the states' tangential momentum is not 0."""
+    q = np.ascontiguousarray(cases.riemann4(40, seed=13)[:, 4:16, 6:26])  # [4, 12, 20]
+    if wall_axis == 0:  # walls west and east, Dirichlet south and north
+        q = np.ascontiguousarray(q[[0, 2, 1, 3]].transpose(0, 2, 1))  # [4, 20, 12]
+    ny, nx = q.shape[1:]
+    dlen = ny if wall_axis == 1 else nx  # cells along a Dirichlet side
+    lo, hi = _boundary_states(dlen, 31), _boundary_states(dlen, 32)
+    if wall_axis == 1:
+        full = np.concatenate([q, _mirror(q, 1)], axis=1)
+        # Dirichlet west/east, states mirrored along y
+        lo_f = np.concatenate([lo, _mirror_states(lo, 1)], axis=1)
+        hi_f = np.concatenate([hi, _mirror_states(hi, 1)], axis=1)
+        kh = (np.full(ny, orc.BND_DIRICHLET, np.uint8), np.full(ny, orc.BND_DIRICHLET, np.uint8),
+              np.full(nx, orc.BND_WALL, np.uint8), np.full(nx, orc.BND_WALL, np.uint8))
+        sh = (lo, hi, None, None)
+        kf = (np.full(2 * ny, orc.BND_DIRICHLET, np.uint8), np.full(2 * ny, orc.BND_DIRICHLET, np.uint8), None, None)
+        sf = (np.ascontiguousarray(lo_f), np.ascontiguousarray(hi_f), None, None)
+        ch = orc.Config(nx=nx, ny=ny, dx=1.0 / 40, limiters=lims, bc_x=1, bc_y=1, bnd_kind=kh, bnd_state=sh)
+        cf = orc.Config(nx=nx, ny=2 * ny, dx=1.0 / 40, limiters=lims, bc_x=1, bc_y=0, bnd_kind=kf, bnd_state=sf)
+    else:
+        full = np.concatenate([q, _mirror(q, 0)], axis=2)
+        lo_f = np.concatenate([lo, _mirror_states(lo, 0)], axis=1)
+        hi_f = np.concatenate([hi, _mirror_states(hi, 0)], axis=1)
+        kh = (np.full(ny, orc.BND_WALL, np.uint8), np.full(ny, orc.BND_WALL, np.uint8),
+              np.full(nx, orc.BND_DIRICHLET, np.uint8), np.full(nx, orc.BND_DIRICHLET, np.uint8))
+        sh = (None, None, lo, hi)
+        kf = (None, None, np.full(2 * nx, orc.BND_DIRICHLET, np.uint8), np.full(2 * nx, orc.BND_DIRICHLET, np.uint8))
+        sf = (None, None, np.ascontiguousarray(lo_f), np.ascontiguousarray(hi_f))
+        ch = orc.Config(nx=nx, ny=ny, dx=1.0 / 40, limiters=lims, bc_x=1, bc_y=1, bnd_kind=kh, bnd_state=sh)
+        cf = orc.Config(nx=2 * nx, ny=ny, dx=1.0 / 40, limiters=lims, bc_x=0, bc_y=1, bnd_kind=kf, bnd_state=sf)
+    assert np.abs(lo[2 - wall_axis]).min() > 0  # tangential momentum at every boundary cell
+    full = np.ascontiguousarray(full)
+    Sh, _ = orc.init(ch, q)
+    Sf, _ = orc.init(cf, full)
+    for _ in range(30):
+        Sh, _, _, ih = orc.step(ch, Sh)
+        Sf, _, _, _ = orc.step(cf, Sf)
+        assert ih.n_bad == 0
+    part = Sf[:, :ny, :] if wall_axis == 1 else Sf[:, :, :nx]
+    err = np.abs(Sh - part).max() / np.abs(Sf).max()
+    assert err < 1e-11, err
