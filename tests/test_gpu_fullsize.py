@@ -138,3 +138,62 @@ def test_rarefaction_bounds_full_size(bound, cache):
     assert d32["n_bad"] == 0 and d32["n_guard"] == 0
     if bound == "LMP":
         assert d32["n_lmp"] == 0
+
+
+@pytest.mark.skipif(os.environ.get("VLBM_LONG_TESTS") != "1",
+                    reason="about four minutes of oracle time on the host cores; set VLBM_LONG_TESTS=1")
+def test_c2_blast_full_horizon_window(cache, capsys):
+    """The 8192^2 blast in the FP64 form (PP + pressure, a = 4 lambda^n,
+    periodic) in the benchmark's launch shape, after the workload's 500 steps.
+
+    A cell's state after n steps depends only on the cells within n of it, so
+    the oracle's run on the central 3072^2 window (periodic wrap) is exact at
+    more than 500 cells from the window's edges, where the wrap's influence
+    has not arrived, provided lambda^n is the full grid's: it is, since the
+    maximum wavespeed lies in the blast (sound speed ~37 against ~0.12 in the
+    quiescent gas) and the blast, whose shock moves at most lambda^n / a^n =
+    1/4 cell per step from the disk of radius 819 cells, stays inside the exact
+    region (radius 1536 - n at step n).  So the central 2072^2 cells, the whole
+    blast, equal the oracle's bit for bit over all 20 planes.  Beyond the
+    window, outside the reach of the blast (more than 819 + 500 cells from the
+    centre), the gas keeps v = 0 exactly and one energy value bit for bit: with
+    uniform pressure and no velocity every term of those components is the
+    same in every cell."""
+    import time
+
+    from paper_2411_15001_amd.solver import Solver
+
+    n, steps, W = 8192, 500, 3072
+    c0 = (n - W) // 2
+    lo, hi = c0 + steps, c0 + W - steps
+    u0 = cases.blast(n, seed=0)
+    ocfg = oracle.Config(nx=n, ny=n, limiters=oracle.RHO_PP | oracle.PRESSURE)
+    s = Solver(u0, **okw(ocfg))
+    s.autotune(cache)
+    s.step(steps)
+    d = s.diagnostics()
+    st = s.get_state()
+    G = st[:, lo:hi, lo:hi].cpu().numpy()
+    m = st[0:4].cpu().numpy()
+    del st
+    s.close()
+    assert d["n_bad"] == 0 and d["n_guard"] == 0
+    uw = np.ascontiguousarray(u0[:, c0:c0 + W, c0:c0 + W])
+    del u0
+    outside = np.ones((n, n), bool)
+    outside[c0:c0 + W, c0:c0 + W] = False
+    assert np.all(m[1][outside] == 0) and np.all(m[2][outside] == 0)
+    Eq = m[3][outside]
+    assert np.all(Eq == Eq[0])
+    del m, outside, Eq
+    wcfg = oracle.Config(nx=W, ny=W, dx=1.0 / n, limiters=oracle.RHO_PP | oracle.PRESSURE)
+    S, _ = oracle.init(wcfg, uw)
+    t0 = time.time()
+    t = 0.0
+    for k in range(0, steps, 50):
+        S, t, info, tot = oracle.run(wcfg, S, 50, t)
+        assert tot[2] == 0
+        with capsys.disabled():
+            print("  oracle C2 window: %d / %d steps, %.0f s" % (k + 50, steps, time.time() - t0), flush=True)
+    assert d["t"] == t
+    assert np.array_equal(G, S[:, lo - c0:hi - c0, lo - c0:hi - c0])
