@@ -29,13 +29,17 @@ and torch's elementwise-kernel bandwidth on the same GPU, with each form's
 achieved bandwidth as a fraction of the faster one.
 
 cpu_baseline: the FP64 CPU oracle (OpenMP over rows, all host cores) timed on
-a bounded sample of the same workload: the blast on a 2048 x 2048 grid for
-80 steps (about 10-20 s of host time).
+a bounded sample of the same workload: the blast on the 8192 x 8192 grid for
+6 steps (about 15 s of host time), and for 1 step on one thread.
 
 Other workloads (`--workload`): `rarefaction` (near-vacuum double
-rarefaction 2048^2, FP64, PP + LMP + pressure, outflow), `batch` (256 uneven
-four-quadrant instances, FP32 state, hipGraph replay) and `adjoint` (gradient
-of a 200-step 512^2 rollout); each prints one JSON line of the same shape.
+rarefaction, 2048^2 by default, PP + LMP or RLMP + pressure, outflow, the
+forms given), `batch` (256 uneven four-quadrant instances, FP32 state,
+hipGraph replay) and `adjoint` (gradient of a 200-step 512^2 rollout); each
+prints one JSON line of the same shape.  The default run also measures the
+8192^2 rarefaction in both forms, the batch and the adjoint (without their
+CPU baselines) and summarises them under `also` in the blast's line;
+`--headline-only` leaves them out.
 """
 from __future__ import annotations
 
@@ -86,6 +90,8 @@ def parse():
     ap.add_argument("--workload", default="blast", choices=["blast", "rarefaction", "batch", "adjoint"],
                     help="blast: the headline 8192^2 line; the others time the LMP, batching and "
                          "differentiation forms on their own workloads")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="blast workload: skip the other workloads that the default run adds under `also`")
     ap.add_argument("--no-per-class", action="store_true",
                     help="batch workload: skip the per-size-class timings")
     ap.add_argument("--record-traffic", nargs="+", metavar="CSV",
@@ -514,13 +520,16 @@ def _timed(fn, steps):
     return e0.elapsed_time(e1)
 
 
-def _line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, roofline, **extra):
+def _line(emit, metric, value, unit, steps, warmup, ms_per_step, dtype, config, roofline, **extra):
+    """One workload's JSON line, printed when emit is set; returned either way."""
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": config, "roofline": roofline}
     out.update(extra)
-    print(json.dumps(out))
+    if emit:
+        print(json.dumps(out))
+    return out
 
 
 def bench_rarefaction(a):
@@ -580,14 +589,14 @@ def bench_rarefaction(a):
             form, forms[form]["value"], avg, 100 * forms[form]["roofline"]["frac"]), file=sys.stderr, flush=True)
     del u0t
     H = forms[forms_req[0]]
-    _line(METRIC, H["value"], "GLUPS", a.steps, a.warmup, H["ms_per_step"],
-          "f32 (theta solve and CFL reduce f64)" if forms_req[0] == "fp32" else "f64",
-          {"workload": "near-vacuum double rarefaction %dx%d, outflow, PP + %s + pressure, "
-                       "a = %g lambda, %s form%s" % (n, n, a.bounds.upper(), 2 * a.beta / (1 - a.alpha),
-                                                     forms_req[0], vdesc), "grid": [n, n]},
-          H["roofline"], status=H["status"], launch=H["launch"], forms=forms,
-          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_rarefaction(min(n, 2048)),
-                                                               {f: v["value"] for f, v in forms.items()})}))
+    return _line(getattr(a, "emit", True), METRIC, H["value"], "GLUPS", a.steps, a.warmup, H["ms_per_step"],
+                 "f32 (theta solve and CFL reduce f64)" if forms_req[0] == "fp32" else "f64",
+                 {"workload": "near-vacuum double rarefaction %dx%d, outflow, PP + %s + pressure, "
+                              "a = %g lambda, %s form%s" % (n, n, a.bounds.upper(), 2 * a.beta / (1 - a.alpha),
+                                                            forms_req[0], vdesc), "grid": [n, n]},
+                 H["roofline"], status=H["status"], launch=H["launch"], forms=forms,
+                 **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_rarefaction(min(n, 2048)),
+                                                                      {f: v["value"] for f, v in forms.items()})}))
 
 
 def bench_batch(a):
@@ -638,16 +647,16 @@ def bench_batch(a):
         per_class[str(side)] = {"instances": len(idx), "cells": cc, "ms_per_step": cms, "launch": cl,
                                 "glups": cc / (cms * 1e-3) / 1e9,
                                 "frac": 160.0 * cc / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    _line(METRIC, cells / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.steps, avg,
-          "f32 (theta solve and CFL reduce f64)",
-          {"workload": "batch of 256 four-quadrant problems, sides 128k with k ~ U{1..8} (seed 0), "
-                       "fp32 state, PP + pressure, outflow, a = 4.4 lambda, hipGraph replay",
-           "instances": 256, "cells": cells},
-          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("batch256_fp32", launch)}, status=int(st),
-          launch=list(launch), per_class=per_class,
-          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_batch(sides, u0s),
-                                                               {"fp32": cells / (avg * 1e-3) / 1e9})}))
+    return _line(getattr(a, "emit", True), METRIC, cells / (avg * 1e-3) / 1e9, "GLUPS", a.steps, a.steps, avg,
+                 "f32 (theta solve and CFL reduce f64)",
+                 {"workload": "batch of 256 four-quadrant problems, sides 128k with k ~ U{1..8} (seed 0), "
+                              "fp32 state, PP + pressure, outflow, a = 4.4 lambda, hipGraph replay",
+                  "instances": 256, "cells": cells},
+                 {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for("batch256_fp32", launch)}, status=int(st),
+                 launch=list(launch), per_class=per_class,
+                 **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_batch(sides, u0s),
+                                                                      {"fp32": cells / (avg * 1e-3) / 1e9})}))
 
 
 def bench_adjoint(a):
@@ -688,17 +697,59 @@ def bench_adjoint(a):
     ms = _timed(lambda: [once() for _ in range(reps)], reps) / reps
     cell_steps = n * n * steps
     ach = (320.0 + 336.0 + 496.0) * cell_steps / (ms * 1e-3) / 1e9
-    _line("cell-steps/s of a forward + adjoint rollout (GLUPS)", cell_steps / (ms * 1e-3) / 1e9,
-          "GLUPS", steps, 0, ms / steps, "f64",
-          {"workload": "gradient of the density misfit after 200 steps w.r.t. u0, 512x512 periodic "
-                       "Gaussian bump, fixed a, checkpoints every 20", "grid": [n, n]},
-          {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": ach / HBM_PEAK_GBS, "traffic": None}, ms_per_gradient=ms,
-          roofline_scope="whole gradient: algorithmic bytes of the forward (320 B), recompute "
-                         "(336 B: state + theta) and adjoint (496 B: U, Ubar in, theta, Ubar out) "
-                         "cell-steps over the gradient time; state copies excluded",
-          **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_adjoint(u0, a_fixed),
-                                                               {"fp64": cell_steps / (ms * 1e-3) / 1e9})}))
+    return _line(getattr(a, "emit", True), "cell-steps/s of a forward + adjoint rollout (GLUPS)",
+                 cell_steps / (ms * 1e-3) / 1e9,
+                 "GLUPS", steps, 0, ms / steps, "f64",
+                 {"workload": "gradient of the density misfit after 200 steps w.r.t. u0, 512x512 periodic "
+                              "Gaussian bump, fixed a, checkpoints every 20", "grid": [n, n]},
+                 {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": ach / HBM_PEAK_GBS, "traffic": None}, ms_per_gradient=ms,
+                 roofline_scope="whole gradient: algorithmic bytes of the forward (320 B), recompute "
+                                "(336 B: state + theta) and adjoint (496 B: U, Ubar in, theta, Ubar out) "
+                                "cell-steps over the gradient time; state copies excluded",
+                 **({} if a.no_cpu else {"cpu_baseline": with_speedup(cpu_adjoint(u0, a_fixed),
+                                                                      {"fp64": cell_steps / (ms * 1e-3) / 1e9})}))
+
+
+def other_workloads(a):
+    """The bounds-limited (8192^2 rarefaction, PP + LMP + pressure, both
+    forms), ensemble and differentiation workloads, each run as its own
+    --workload run would (without its CPU baseline), summarised for the blast
+    line's `also` so that one default run measures every workload.  A failure
+    is recorded in place of that workload's figures."""
+    import copy
+
+    import torch
+
+    jobs = [("rarefaction8192_lmp", bench_rarefaction, {"n": 8192, "forms": "fp64,fp32", "bounds": "lmp"}),
+            ("batch256", bench_batch, {"no_per_class": True}),
+            ("adjoint512", bench_adjoint, {})]
+    out = {}
+    for name, fn, over in jobs:
+        b = copy.copy(a)
+        b.no_cpu, b.emit = True, False
+        for k, v in over.items():
+            setattr(b, k, v)
+        try:
+            L = fn(b)
+        except Exception as e:  # keep the headline line; say what failed
+            out[name] = {"error": repr(e)}
+            print("# also %s: failed: %r" % (name, e), file=sys.stderr, flush=True)
+            continue
+        finally:
+            torch.cuda.empty_cache()
+        e = {"workload": L["config"]["workload"], "metric": L["metric"], "value": L["value"],
+             "unit": L["unit"], "ms_per_step": L["ms_per_step"], "steps": L["steps"], "roofline": L["roofline"]}
+        for k in ("launch", "ms_per_gradient", "roofline_scope"):
+            if k in L:
+                e[k] = L[k]
+        if "forms" in L:
+            e["forms"] = {f: {"value": v["value"], "ms_per_step": v["ms_per_step"], "launch": v["launch"],
+                              "roofline": v["roofline"]} for f, v in L["forms"].items()}
+        out[name] = e
+        print("# also %s: %.3f %s, %.1f%% of HBM peak" % (name, L["value"], L["unit"], 100 * L["roofline"]["frac"]),
+              file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -782,6 +833,8 @@ def main():
                              "frac": {k: v["roofline"]["achieved"] / best for k, v in forms.items()}}
     if a.calib_gib > 0:
         out["calibration_copy"] = calibration_copy(a.calib_gib)
+    if not a.headline_only:
+        out["also"] = other_workloads(a)
     if not a.no_cpu:
         if "fp32" in forms and not a.no_oracle_error:
             out["fp32_error_vs_oracle"] = fp32_error_vs_oracle()

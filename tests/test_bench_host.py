@@ -69,3 +69,43 @@ def test_traffic_lookup_matches_launch_shape():
         # missing trailing launch values read as 0
         assert bench.traffic_for(key, launch[:2]) == (got if all(v == 0 for v in launch[2:]) else None)
     assert bench.traffic_for("no_such_workload", [64, 4]) is None
+
+
+def test_other_workloads_summarise_and_keep_going(monkeypatch):
+    """The default run's `also`: each other workload runs without its CPU
+    baseline and without printing its own line, is summarised (forms and
+    roofline kept), and a failing one is recorded in place of its figures
+    without losing the others."""
+    import bench
+
+    seen = []
+
+    def fake(name):
+        def run(b):
+            seen.append((name, b.no_cpu, b.emit, getattr(b, "n", None), getattr(b, "forms", None)))
+            if name == "batch":
+                raise RuntimeError("no device")
+            line = {"config": {"workload": name}, "metric": "m", "value": 1.0, "unit": "GLUPS",
+                    "ms_per_step": 2.0, "steps": 5, "roofline": {"frac": 0.5}}
+            if name == "rarefaction":
+                line["forms"] = {"fp64": {"value": 1.0, "ms_per_step": 2.0, "launch": [256, 1, 4, 0],
+                                          "roofline": {"frac": 0.5}, "diag": {}}}
+            return line
+        return run
+
+    monkeypatch.setattr(bench, "bench_rarefaction", fake("rarefaction"))
+    monkeypatch.setattr(bench, "bench_batch", fake("batch"))
+    monkeypatch.setattr(bench, "bench_adjoint", fake("adjoint"))
+    import sys
+
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert a.headline_only is False
+    out = bench.other_workloads(a)
+    assert set(out) == {"rarefaction8192_lmp", "batch256", "adjoint512"}
+    assert "error" in out["batch256"] and "no device" in out["batch256"]["error"]
+    assert out["rarefaction8192_lmp"]["forms"]["fp64"]["launch"] == [256, 1, 4, 0]
+    assert "diag" not in out["rarefaction8192_lmp"]["forms"]["fp64"]
+    assert all(no_cpu and not emit for _, no_cpu, emit, _, _ in seen)
+    assert ("rarefaction", True, False, 8192, "fp64,fp32") in seen
+    assert a.no_cpu is False  # the caller's options are not changed
