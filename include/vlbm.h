@@ -27,9 +27,11 @@
  * {rho, m1, m2, E}; each plane holds the instances one after the other,
  * instance i as [ny_i][nx_i] row-major.  Element type: float64 (LBM_FP64)
  * or float32 (LBM_FP32_STATE).  A context may keep the same values in
- * another order in its own workspace buffers (a single instance whose width
- * is a multiple of 64 keeps the 20 values of every 64-cell run of a row
- * together); the calls that copy to or from caller buffers convert.
+ * another order in its own workspace buffers (when every instance's width is
+ * a multiple of 64, with face blending and no boundary descriptions, the 20
+ * values of every 64-cell run of a row lie together, each instance's state
+ * after the ones before it); the calls that copy to or from caller buffers
+ * convert.
  *
  * Streams: every enqueueing call is asynchronous on the stream given to the
  * init call (a hipStream_t passed as void*; NULL = default stream).  A context
