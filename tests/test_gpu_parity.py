@@ -342,7 +342,10 @@ def test_c1_full_size(tmp_path, capsys):
     committed autotune cache): after the workload's 1000 steps the state equals
     the oracle's bit for bit (the oracle runs on the host's cores meanwhile,
     about three minutes, printing its progress), every step stayed admissible
-    and every new density inside its LMP bounds."""
+    and every new density inside its LMP bounds.  The FP32-state form of the
+    same run, in its own launch shape, stays admissible and within the
+    precision form's 1e-4 relative L1 of the oracle's density after the 1000
+    steps."""
     import os
     import shutil
     import time
@@ -360,6 +363,13 @@ def test_c1_full_size(tmp_path, capsys):
     G = s.get_state().cpu().numpy()
     m = s.moments().cpu().numpy()  # raises on a positivity event
     s.close()
+    s32 = Solver(u0, precision=B.LBM_FP32_STATE, **okw(ocfg))
+    s32.autotune(cache)
+    s32.step(steps)
+    d32 = s32.diagnostics()
+    rho32 = s32.moments().cpu().numpy()[0]
+    s32.close()
+    assert d32["n_bad"] == 0 and d32["n_guard"] == 0
     assert d["n_bad"] == 0 and d["n_guard"] == 0
     # the new density never left the eq. (29) bounds over the 1000 steps
     assert d["n_lmp"] == 0
@@ -377,6 +387,11 @@ def test_c1_full_size(tmp_path, capsys):
     assert tot[2] == 0 and tot[3] == 0
     assert np.array_equal(G, S), "max rel err %.3e" % rel_err(G, S)
     assert d["n_limited"] == tot[1]
+    e32 = np.abs(rho32 - S[0]).sum() / np.abs(S[0]).sum()
+    with capsys.disabled():
+        print("  C1 FP32 form: rel L1 rho vs oracle after %d steps %.3e, LMP check %d" % (steps, e32, d32["n_lmp"]),
+              flush=True)
+    assert e32 <= 1e-4
 
 
 def test_fp32_form_against_oracle():
