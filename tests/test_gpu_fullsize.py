@@ -70,7 +70,12 @@ def test_c3_batch_full_size(cache):
     single-instance runs; in the FP64 form the workload's 500 steps (graph
     replays) leave the first instance of each side 128, 256, 384 and 512 and
     the largest one bit-identical to their oracle runs, with the same lambda
-    and time (about half a minute of oracle time)."""
+    and time.  The FP32 ensemble after the same 500 steps stays admissible;
+    its density error against the oracle is held to 1e-4 plus five times the
+    oracle's own spread from one float32 rounding of u0 (these four-quadrant
+    flows become sensitive by then: that spread reaches 2e-3 to 9e-2, while
+    float32 rounds the state at every step), and to 1e-4 outright on the
+    128^2 instance, which stays resolved (about a minute of oracle time)."""
     from paper_2411_15001_amd.solver import BatchSolver, Solver
 
     sides = cases.batch_sides(256, seed=0)
@@ -91,7 +96,11 @@ def test_c3_batch_full_size(cache):
 
     bs = BatchSolver(u0s, **kw)
     bs.step_graph(500)
+    b32 = BatchSolver(u0s, precision=B.LBM_FP32_STATE, **kw)
+    b32.autotune(cache)
+    b32.step_graph(500)
     pick = sorted({sides.index(k) for k in (128, 256, 384, 512)} | {int(np.argmax(sides))})
+    errs = {}
     for i in pick:
         n = sides[i]
         ocfg = oracle.Config(nx=n, ny=n, dx=1.0 / n, limiters=oracle.RHO_PP | oracle.PRESSURE,
@@ -102,7 +111,23 @@ def test_c3_batch_full_size(cache):
         d = bs.diagnostics(i)
         assert np.array_equal(bs.moments(i).cpu().numpy(), S[0:4]), (i, n)
         assert d["lam"] == info.lambda_new and d["t"] == t, (i, n)
+        assert b32.diagnostics(i)["n_bad"] == 0, i
+        if n > 512:
+            continue
+        r32 = b32.moments(i, check=False)[0].cpu().numpy()[0]
+        e = float(np.abs(r32 - S[0]).sum() / np.abs(S[0]).sum())
+        # the oracle's own spread from one float32 rounding of u0
+        rng = np.random.default_rng(1)
+        Sp, _ = oracle.init(ocfg, u0s[i] * (1 + 6e-8 * rng.uniform(-1, 1, u0s[i].shape)))
+        Sp, _, _, _ = oracle.run(ocfg, Sp, 500)
+        floor = float(np.abs(Sp[0] - S[0]).sum() / np.abs(S[0]).sum())
+        errs[(i, n)] = (e, floor)
     bs.close()
+    b32.close()
+    print("FP32 ensemble, rel L1 rho vs oracle after 500 steps (error, oracle floor):", errs)
+    for (i, n), (e, floor) in errs.items():
+        assert e <= 1e-4 + 5 * floor, (i, n, e, floor)
+    assert errs[(sides.index(128), 128)][0] <= 1e-4
 
 
 @pytest.mark.parametrize("bound", ["LMP", "RLMP"])
