@@ -1546,26 +1546,6 @@ __device__ __forceinline__ void march_short_dma(const StepArgs& A, const Inst& i
     __builtin_amdgcn_sched_barrier(0);
     if (L + 2 <= y1) issue(L + 2, b == 0 ? 2 : b - 1);
     __builtin_amdgcn_sched_barrier(0);
-    if (L == y0 - 1) {
-      // the row below the strip produces nothing: only the values that the
-      // next iteration carries (its y-face's left state) are computed, by the
-      // same expressions as below
-      const T* rv = (const T*)(ring + b * dma_row_bytes<T>());
-      C u0[4], f0[4], g0[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) u0[c] = (C)rv[c * 64 + lane];
-      fluxes(u0, K.gm1, f0, g0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const C m3 = maxw(2, u0[c], f0[c], g0[c], K.w, K.r2a);
-        pu[c] = u0[c];
-        pg[c] = g0[c];
-        pM3[c] = m3;
-        pd3[c] = m3 - (C)rv[(12 + c) * 64 + lane];
-      }
-      b = b == 2 ? 0 : b + 1;
-      continue;
-    }
     const unsigned char* rb = ring + b * dma_row_bytes<T>();
     const T* rowv = (const T*)rb;
     const T* hrow = (const T*)(rb + 20 * 64 * (int)sizeof(T));
