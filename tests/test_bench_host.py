@@ -2,6 +2,7 @@
 record's link to the kernel source, and the measured-traffic lookup."""
 import json
 import os
+import re
 import subprocess
 import sys
 
@@ -109,3 +110,30 @@ def test_other_workloads_summarise_and_keep_going(monkeypatch):
     assert all(no_cpu and not emit for _, no_cpu, emit, _, _ in seen)
     assert ("rarefaction", True, False, 8192, "fp64,fp32") in seen
     assert a.no_cpu is False  # the caller's options are not changed
+
+
+def test_traffic_records_use_the_committed_launch_shapes():
+    """Every counter record was taken in the launch shape that the committed
+    autotune cache gives its workload, so the default benchmark run, which
+    reads its shapes from that cache, finds a record (a shape changed in one
+    file and not the other would leave `traffic` null)."""
+    with open(os.path.join(ROOT, "paper_2411_15001_amd", "autotune_cache.json")) as f:
+        cache = json.load(f)
+    # record key -> (instances, nx, precision, limiter set, boundary conditions)
+    want = {"blast8192_fp32": ("1", "8192", "1", "9", "00"), "blast8192_fp64": ("1", "8192", "0", "9", "00"),
+            "rarefaction8192_fp32": ("1", "8192", "1", "11", "11"),
+            "rarefaction8192_fp64": ("1", "8192", "0", "11", "11"),
+            "rarefaction8192_rlmp_fp32": ("1", "8192", "1", "13", "11"),
+            "rarefaction8192_rlmp_fp64": ("1", "8192", "0", "13", "11"),
+            "rarefaction2048_fp64": ("1", "2048", "0", "11", "11"), "batch256_fp32": ("256", None, "1", "9", "11")}
+    rec = _record()
+    for key, (n, nx, prec, lims, bc) in want.items():
+        assert key in rec, key
+        hits = []
+        for ck, shape in cache.items():
+            m = re.match(r"n(\d+)_nx(\d+)_ny\d+_cells\d+_p(\d)_lim(\d+)_o2_bc(\d\d)_s0_b0_h", ck)
+            if m and m.group(1) == n and (nx is None or m.group(2) == nx) and m.group(3) == prec \
+                    and m.group(4) == lims and m.group(5) == bc:
+                hits.append(shape)
+        assert len(hits) == 1, (key, hits)
+        assert list(hits[0]) == list(rec[key]["launch"]), (key, hits[0], rec[key]["launch"])
